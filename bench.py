@@ -1,0 +1,266 @@
+#!/usr/bin/env python
+"""Throughput of the SplitSolve hot path on one MI355X: (E, k) solves per second.
+
+One step = the whole hot path for every (E, k) instance of the workload, inputs resident in HBM:
+lead self-energies (decimation), Q = first/last block columns of (E S - H)^{-1} (Alg. 1 with
+pivoted LU), the 2s x 2s open-boundary correction with psi for m injected columns and the corner of
+G^R, and the Caroli transmission T_LR, T_RL.
+
+Workloads (synthetic, seeded; see synth/):
+  dft512   s = 512 (8x8x8 lattice slab), nb = 40, 64 energies in [-5, 5] eV x 4 momenta
+           k in {pi/8, 3pi/8, 5pi/8, 7pi/8}, seed 1, crystal device, complex128   (default)
+  chain16  s = 16 random chain cell, nb = 32, 64 energies in [-3, 3], seed 0, complex128
+
+Prints one JSON line.  --gpus > 1 is refused: this build measures one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FP64_PEAK_TFLOPS = 78.6   # MI355X dense FP64 matrix, datasheet
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    "dft512": dict(s=512, nb=40, n_e=64, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8],
+                   seed=1, eta=1e-8, m=32, chunk=64),
+    "chain16": dict(s=16, nb=32, n_e=64, e_lo=-3.0, e_hi=3.0, ks=[0.0], seed=0, eta=1e-8, m=4, chunk=64),
+}
+
+
+def sweep_flops(nb: int, s: int) -> float:
+    """Algorithmic flops of Q for one instance (both recursions + chains), 8mnk per complex GEMM,
+    8/3 n^3 per complex LU, 8 n^2 k per triangular pair with k right-hand sides."""
+    per_step = 8 * s**3 + 8.0 / 3 * s**3 + 8 * s**3  # D update, LU, solve with s RHS
+    chain = 8 * s**3
+    return 2 * (nb * per_step - 8 * s**3 + (nb - 1) * chain)
+
+
+def dec_flops(s: int, iters: float) -> float:
+    """Decimation pass: LU of eps, solve with 2s RHS, four s^3 products; plus the final Sigma solves."""
+    return iters * (8.0 / 3 * s**3 + 16 * s**3 + 32 * s**3)
+
+
+def obc_flops(nb: int, s: int, m: int) -> float:
+    n = 2 * s
+    cq = 8 * n * n * s
+    lu = 8.0 / 3 * n**3 + 8 * n * n * (n + m)
+    gc = 8 * n**3
+    psi = 8 * nb * s * n * m + 8 * n * n * m
+    return cq + lu + gc + psi
+
+
+def build_inputs(name: str):
+    import synth
+
+    w = WORKLOADS[name]
+    s, nb = w["s"], w["nb"]
+    if name == "chain16":
+        cells = [synth.chain_cell(s, w["seed"])]
+    else:
+        base = synth.DFTLikeCell(synth.SLAB_SHAPES[s], w["seed"])
+        cells = [base.at(k) for k in w["ks"]]
+    insts = [synth.device_from_cell(c, nb) for c in cells]
+    energies = np.linspace(w["e_lo"], w["e_hi"], w["n_e"])
+    E = np.tile(energies, len(cells))
+    kidx = np.repeat(np.arange(len(cells), dtype=np.int32), len(energies))
+    inj = np.stack([synth.injection_block(s, w["m"], 1000 + b) for b in range(len(E))])
+    return w, insts, E, kidx, inj
+
+
+def cpu_baseline(w, insts, E, kidx, inj, sample: int, T_gpu):
+    """The oracle, untuned, on `sample` instances (all host cores BLAS offers); returns the JSON object."""
+    from oracle import transport
+
+    idx = np.linspace(0, len(E) - 1, sample).round().astype(int)
+    t0 = time.perf_counter()
+    errs = []
+    for b in idx:
+        inst = insts[kidx[b]]
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
+                                       inst.S01, float(E[b]), w["eta"], inj=inj[b])
+        errs.append(max(abs(T_gpu[b, 0] - ref["t_lr"]) / max(1.0, abs(ref["t_lr"])),
+                        abs(T_gpu[b, 1] - ref["t_rl"]) / max(1.0, abs(ref["t_rl"]))))
+    dt = time.perf_counter() - t0
+    try:
+        import threadpoolctl
+        cores = max(p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()) or os.cpu_count()
+    except Exception:
+        cores = os.cpu_count()
+    return dict(value=len(idx) / dt, unit="solves/s", cores=int(cores), kind="oracle",
+                sample=f"{len(idx)} of {len(E)} instances (indices {idx.tolist()}), same inputs, "
+                       f"{dt:.1f} s wall"), float(max(errs))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS))
+    ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
+    ap.add_argument("--roofline-kernel", default="dec_update",
+                    help="kernel family timed with HIP events for the roofline entry")
+    ap.add_argument("--cpu-sample", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: run with --gpus 1 (this build has no multi-GPU path)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1812_01396_amd as ss
+
+    w, insts, E_np, kidx_np, inj_np = build_inputs(args.workload)
+    s, nb, m = w["s"], w["nb"], w["m"]
+    chunk = args.chunk or w["chunk"]
+    nbatch = len(E_np)
+    dev = torch.device("cuda", 0)
+
+    def t(a, dt=torch.complex128):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+
+    Hd = t(np.stack([i.Hd for i in insts]))
+    Hu = t(np.stack([i.Hu for i in insts]))
+    Sd = t(np.stack([i.Sd for i in insts]))
+    Su = t(np.stack([i.Su for i in insts]))
+    H00, H01, S00, S01 = (t(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01"))
+    E = t(E_np, torch.float64)
+    kidx = t(kidx_np, torch.int32)
+    inj = t(inj_np)
+    sigma = torch.empty(nbatch, 2, s, s, dtype=torch.complex128, device=dev)
+    iters = torch.empty(nbatch, dtype=torch.int32, device=dev)
+    resid = torch.empty(nbatch, 2, dtype=torch.float64, device=dev)
+    info_s = torch.empty(nbatch, dtype=torch.int32, device=dev)
+    Qbuf = torch.empty(chunk, nb, s, 2 * s, dtype=torch.complex128, device=dev)
+    psi = torch.empty(nbatch, nb, s, m, dtype=torch.complex128, device=dev)
+    gc = torch.empty(nbatch, 2 * s, 2 * s, dtype=torch.complex128, device=dev)
+    T = torch.empty(nbatch, 2, dtype=torch.float64, device=dev)
+    info_q = torch.empty(nbatch, dtype=torch.int32, device=dev)
+    info_o = torch.empty(nbatch, dtype=torch.int32, device=dev)
+
+    stream_main = torch.cuda.current_stream(dev)
+    stream_obc = torch.cuda.Stream(dev)
+    ctx = ss.Context(0, stream_main)
+    ctx_s = ss.Context(0, stream_obc)
+    fam = args.roofline_kernel
+    sig_ctx_families = {"dec_update"}
+
+    ss.splitsolve._check_kidx(kidx, len(insts))  # validated once here; the hot loop skips the host sync
+
+    def step():
+        # self-energies on their own stream, overlapping the first chunks' recursions; the previous
+        # step's readers of sigma on the main stream must finish before it is overwritten
+        prev = torch.cuda.Event()
+        prev.record(stream_main)
+        done = torch.cuda.Event()
+        err = []
+
+        def run_sigma():
+            try:
+                with torch.cuda.stream(stream_obc):
+                    stream_obc.wait_event(prev)
+                    ss.ss_lead_selfenergy(ctx_s, H00, H01, S00, S01, E, w["eta"], kidx=kidx, sigma=sigma,
+                                          iters=iters, resid=resid, info=info_s, validate=False)
+                    done.record(stream_obc)
+            except Exception as e:  # surfaced after join
+                err.append(e)
+
+        th = threading.Thread(target=run_sigma)
+        th.start()
+        for c0 in range(0, nbatch, chunk):
+            c1 = min(c0 + chunk, nbatch)
+            q = Qbuf[: c1 - c0]
+            ss.ss_precompute_columns(ctx, Hd, Hu, Sd, Su, E[c0:c1], kidx=kidx[c0:c1], Q=q, info=info_q[c0:c1],
+                                     validate=False)
+            if c0 == 0:
+                th.join()
+                if err:
+                    raise err[0]
+                stream_main.wait_event(done)
+            ss.ss_apply_obc(ctx, q, sigma[c0:c1], inj=inj[c0:c1], psi=psi[c0:c1], gc=gc[c0:c1],
+                            info=info_o[c0:c1])
+            ss.ss_transmission(ctx, gc[c0:c1], sigma[c0:c1], T=T[c0:c1])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    timed_ctx = ctx_s if fam in sig_ctx_families else ctx
+    timed_ctx.kernel_timer(fam)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    k_ms, k_launches = timed_ctx.kernel_timer_read()
+    timed_ctx.kernel_timer(None)
+
+    it_np = iters.cpu().numpy().astype(np.float64)
+    T_np = T.cpu().numpy()
+    bad = int((info_s.cpu() != 0).sum() + (info_q.cpu() != 0).sum() + (info_o.cpu() != 0).sum())
+    ms_per_step = elapsed * 1e3 / args.steps
+    value = nbatch * args.steps / elapsed
+
+    # algorithmic flops of one step
+    f_sweep = nbatch * sweep_flops(nb, s)
+    f_dec = dec_flops(s, float(it_np.sum()))
+    f_obc = nbatch * obc_flops(nb, s, m)
+    f_step = f_sweep + f_dec + f_obc
+    fam_flops = {
+        "dec_update": args.steps * 32.0 * s**3 * float(it_np.sum()),
+        "form": args.steps * nbatch * 2 * (nb - 1) * 8.0 * s**3,
+        "chain": args.steps * nbatch * 2 * (nb - 1) * 8.0 * s**3,
+    }
+    roof = None
+    if k_launches > 0 and fam in fam_flops:
+        achieved = fam_flops[fam] / (k_ms * 1e-3) / 1e12
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None, kernel=fam,
+                    launches=int(k_launches), avg_launch_ms=round(k_ms / k_launches, 4))
+
+    cpu = None
+    t_err = None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        cpu, t_err = cpu_baseline(w, insts, E_np, kidx_np, inj_np, args.cpu_sample, T_np)
+
+    out = {
+        "metric": "(E,k) solves/sec",
+        "value": round(value, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "s": s, "nb": nb, "instances": nbatch, "energies": w["n_e"],
+                   "k_points": len(w["ks"]), "m_inj": m, "eta": w["eta"], "chunk": chunk,
+                   "precision": "fp64"},
+        "tflops_step": round(f_step / (ms_per_step * 1e-3) / 1e12, 3),
+        "frac_fp64_peak_step": round(f_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+        "decimation_iters": [int(it_np.min()), int(it_np.max()), round(float(it_np.mean()), 2)],
+        "nonzero_info": bad,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "t_err_vs_oracle": t_err,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,160 @@
+/* splitsolve.h — C ABI of the SplitSolve hot path for one AMD MI355X (gfx950).
+ *
+ * Problem (Sec. 2B, Eq. (wf)): for a block-tridiagonal Hamiltonian H and overlap S with n_B = nb
+ * diagonal blocks of size s, at real energy E, solve
+ *
+ *     (E*S - H - Sigma_L - Sigma_R) psi = Inj
+ *
+ * where Sigma_L acts on the first and Sigma_R on the last diagonal block.  SplitSolve (Sec. 3B)
+ * splits this into a pre-processing step that needs only A = E*S - H (the first and last block
+ * columns Q of A^{-1}, Step 1 / Alg. 1) and a post-processing step that folds the boundary
+ * self-energies in through a 2s x 2s correction (Sherman-Morrison-Woodbury, Eq. (x), Steps 2-4).
+ *
+ * Conventions for every entry point
+ * ---------------------------------
+ *  - Complex numbers are ss_c128 = {double re, im} (the layout of C99 double complex and of
+ *    torch.complex128).  Matrices are ROW-MAJOR and contiguous; a "[a][b][c]" shape lists the
+ *    dimensions from slowest to fastest.
+ *  - ALL array pointers are DEVICE pointers, owned by the caller.  The library never frees or keeps
+ *    caller memory beyond the call; it owns only its context's workspaces.
+ *  - Calls are asynchronous on the context's HIP stream: they return once the work is enqueued.
+ *    Read outputs after synchronizing that stream (or ss_synchronize).
+ *  - Host-detectable problems (null pointers, sizes out of range, a failed HIP call) are returned as
+ *    ss_status; the context keeps a message for ss_last_error.  Nothing is printed, nothing thrown.
+ *  - Numerical outcomes are written per instance to a caller-owned device int array `info`
+ *    (LAPACK style, see each call).  NaN/Inf inputs propagate to the outputs.
+ *  - H and S are Hermitian: only the diagonal blocks H_{i,i} and the upper blocks H_{i,i+1} are
+ *    passed; the lower blocks are H_{i+1,i} = H_{i,i+1}^H (likewise for S).
+ *  - Many (E, k) instances run in one call ("batch").  `nk` (H, S) sets are stored back to back;
+ *    instance b uses set kidx[b] (kidx == NULL means set b % nk) and energy E[b].
+ *  - One context serves one host thread; calls on one context are ordered on its stream.
+ */
+#ifndef SPLITSOLVE_H
+#define SPLITSOLVE_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ss_ctx ss_ctx;
+
+typedef struct {
+  double re, im;
+} ss_c128;
+
+typedef enum {
+  SS_OK = 0,
+  SS_ERR_ARG = 1,         /* invalid argument (null pointer, size out of range)            */
+  SS_ERR_NOMEM = 2,       /* device workspace allocation failed                             */
+  SS_ERR_DEVICE = 3,      /* a HIP runtime call failed (launch, copy, synchronization)      */
+  SS_ERR_UNSUPPORTED = 4  /* a well-formed request outside what this build implements       */
+} ss_status;
+
+/* Largest block size accepted (the 2s x 2s corner system needs 2s <= 2048). */
+#define SS_MAX_S 1024
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream` (a hipStream_t; NULL means
+ * the device's default stream).  Workspaces are allocated lazily and grow as needed. */
+ss_status ss_create(ss_ctx **ctx, int device, void *hip_stream);
+/* Release the context and its workspaces (waits for its stream first).  NULL is a no-op. */
+void ss_destroy(ss_ctx *ctx);
+/* Redirect later calls to another stream of the same device. */
+ss_status ss_set_stream(ss_ctx *ctx, void *hip_stream);
+/* Block the host until the context's stream has drained. */
+ss_status ss_synchronize(ss_ctx *ctx);
+/* Static text for a status code, and the detail of the context's last failure ("" if none). */
+const char *ss_status_string(ss_status st);
+const char *ss_last_error(const ss_ctx *ctx);
+/* Bytes of device workspace the context currently holds. */
+size_t ss_workspace_bytes(const ss_ctx *ctx);
+
+/* Kernel timing probe (a profiling aid).  ss_kernel_timer(ctx, family) waits for the stream, clears
+ * the accumulated time and from then on brackets every launch of that kernel family on this context
+ * with a pair of HIP events on the context's stream (NULL or "" switches the probe off).
+ * ss_kernel_timer_read waits for the stream and returns the summed event time in milliseconds and
+ * the number of timed launches since the last read, then clears them.  Families: "form" (diagonal
+ * block formation and product of the recursion), "chain" (Q_i = -X_i Q_{i-1}), "panel",
+ * "panel_update", "row_block", "back_sub" (LU and triangular solves), "dec_update" (decimation pass
+ * products), "obc" (corner system and psi products), "trans" (transmission). */
+ss_status ss_kernel_timer(ss_ctx *ctx, const char *family);
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches);
+
+/* ---------------------------------------------------------------- inputs */
+
+typedef struct {
+  int nb;                 /* number of diagonal blocks n_B >= 1                                */
+  int s;                  /* block size, 1 <= s <= SS_MAX_S                                    */
+  int nk;                 /* number of (H, S) sets stored back to back, >= 1                   */
+  const ss_c128 *H_diag;  /* [nk][nb][s][s]    H_{i,i}                                          */
+  const ss_c128 *H_upper; /* [nk][nb-1][s][s]  H_{i,i+1}  (ignored when nb == 1)                */
+  const ss_c128 *S_diag;  /* [nk][nb][s][s]    S_{i,i}   (S is required; pass I for S = 1)      */
+  const ss_c128 *S_upper; /* [nk][nb-1][s][s]  S_{i,i+1}                                        */
+} ss_btd;
+
+/* ---------------------------------------------------------------- the four steps */
+
+/* Boundary self-energies of a periodic lead (Sec. 3A: the OBCs; computed here by the iterative
+ * decimation technique the section names as the standard alternative to FEAST).
+ *
+ * The lead cell (H00, H01, S00, S01), each [nk][s][s], repeats to infinity on both sides.  With
+ * a0 = (E + i*eta) S00 - H00, a1 = E S01 - H01, am1 = a1^H (eta enters the diagonal cell only):
+ *     Sigma_L = am1 g_L a1,  g_L = (a0 - am1 g_L a1)^{-1}   (lead on the left of block 1)
+ *     Sigma_R = a1 g_R am1,  g_R = (a0 - a1 g_R am1)^{-1}   (lead on the right of block n_B)
+ * Decimation doubles the eliminated chain each pass and stops once
+ * max|alpha| + max|beta| <= tol * max|a0| (tol <= 0 means 1e-14), or after max_iter passes
+ * (max_iter <= 0 means 200).
+ *
+ * Outputs: sigma [batch][2][s][s] (Sigma_L then Sigma_R); optional (may be NULL): iters [batch]
+ * (passes used), resid [batch][2] (relative Frobenius residual of the fixed-point equation,
+ * ||Sigma - a (a0 - Sigma)^{-1} a'|| / ||Sigma||, left then right), info [batch]:
+ *   0 converged;  -1 not converged within max_iter (last iterate returned);
+ *   k > 0: an exactly zero pivot at column k-1 of a factorization. */
+ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00,
+                             const ss_c128 *H01, const ss_c128 *S00, const ss_c128 *S01,
+                             const int *kidx, const double *E, double eta, double tol,
+                             int max_iter, ss_c128 *sigma, int *iters, double *resid, int *info);
+
+/* Step 1 (Sec. 3B, Alg. 1): Q = [A^{-1}_{:,1}, A^{-1}_{:,n_B}] for A = E*S - H.
+ *
+ * Backward recursion X_{n_B+1} = 0, (A_{i,i} - A_{i,i+1} X_{i+1}) X_i = A_{i,i-1} with A_{1,0} := I,
+ * then Q_i = -X_i Q_{i-1} from Q_0 = -I, gives the first block column; the mirrored recursion (from
+ * block 1 upwards with A_{n_B,n_B+1} := I) gives the last one.  Each diagonal system is solved by LU
+ * with partial pivoting on the GPU.
+ *
+ * Output Q [batch][nb][s][2s]: block row i holds (A^{-1})_{i,1} in columns [0, s) and
+ * (A^{-1})_{i,n_B} in columns [s, 2s).  info [batch] (may be NULL): 0, or 1 + (i-1)*s + c for an
+ * exactly zero pivot in column c of the i-th diagonal system (1-based i; the smallest such code over
+ * both recursions). */
+ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx,
+                                const double *E, ss_c128 *Q, int *info);
+
+/* Steps 2-4 (Sec. 3B, Eq. (x)): fold the boundary self-energies in and recover the wave function.
+ *
+ * With C Q = [Sigma_L Q_{1,:}; Sigma_R Q_{n_B,:}] (2s x 2s), R = I - C Q, b' = inj (the non-zero
+ * rows of Inj: first block row on top, last block row below) and z = R^{-1} (C Q) b':
+ *     psi = Q (b' + z)                      [batch][nb][s][m]
+ *     gc  = [Q_{1,:}; Q_{n_B,:}] R^{-1}     [batch][2s][2s]: the corner blocks
+ *           [[G_11, G_1n], [G_n1, G_nn]] of G^R = (A - Sigma)^{-1} (Sec. 2B, Eq. (negf)).
+ * Q and sigma are the outputs of the two calls above.  m >= 0 (m == 0: inj and psi may be NULL);
+ * gc may be NULL.  info [batch] (may be NULL): 0, or 1 + c for an exactly zero pivot in column c
+ * of R. */
+ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q,
+                       const ss_c128 *sigma, int m, const ss_c128 *inj, ss_c128 *psi,
+                       ss_c128 *gc, int *info);
+
+/* Caroli transmission from the corner of G^R (the product the hot path ends with):
+ *     T_LR = Re Tr[Gamma_L G_1n Gamma_R G_1n^H],  T_RL = Re Tr[Gamma_R G_n1 Gamma_L G_n1^H],
+ * Gamma = i (Sigma - Sigma^H).  gc [batch][2s][2s] from ss_apply_obc, sigma [batch][2][s][s].
+ * Output T [batch][2] = (T_LR, T_RL). */
+ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
+                          double *T);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SPLITSOLVE_H */

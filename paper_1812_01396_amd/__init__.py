@@ -1,0 +1,16 @@
+"""SplitSolve hot path for one AMD MI355X (gfx950): HIP kernels behind a C ABI, with a ctypes binding.
+
+The library computes, for many (E, k) instances of a block-tridiagonal Hamiltonian/overlap pair,
+the lead self-energies, the first and last block columns of (E S - H)^{-1} (SplitSolve pre-processing),
+the open-boundary correction with the wave function and the corner of G^R (post-processing), and the
+Caroli transmission.  See include/splitsolve.h for the ABI.
+"""
+from .splitsolve import (  # noqa: F401
+    Context,
+    SplitSolveError,
+    load_library,
+    ss_apply_obc,
+    ss_lead_selfenergy,
+    ss_precompute_columns,
+    ss_transmission,
+)

@@ -1,0 +1,221 @@
+// C ABI entry points: argument validation, context and workspace management.
+#include <cstdio>
+#include <new>
+
+#include "drivers.hpp"
+#include "lu.hpp"
+
+namespace ss {
+
+ss_status fail(ss_ctx *ctx, ss_status st, const std::string &msg) {
+  if (ctx) ctx->err = msg;
+  return st;
+}
+
+ss_status check_launch(ss_ctx *ctx, const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(ctx, SS_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return SS_OK;
+}
+
+ss_status workspace(ss_ctx *ctx, Slot s, size_t bytes, void **out) {
+  Buffer &b = ctx->slot[s];
+  if (bytes == 0) bytes = 256;
+  if (b.bytes < bytes) {
+    if (b.ptr) {
+      if (hipStreamSynchronize(ctx->stream) != hipSuccess)
+        return fail(ctx, SS_ERR_DEVICE, "workspace: stream synchronize before reallocation failed");
+      (void)hipFree(b.ptr);
+      b.ptr = nullptr;
+      b.bytes = 0;
+    }
+    const size_t want = bytes + bytes / 8;
+    if (hipMalloc(&b.ptr, want) != hipSuccess) {
+      (void)hipGetLastError();
+      b.ptr = nullptr;
+      return fail(ctx, SS_ERR_NOMEM, "workspace: device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.bytes = want;
+  }
+  *out = b.ptr;
+  return SS_OK;
+}
+
+ss_status host_word(ss_ctx *ctx, int **out) {
+  if (!ctx->host_word) {
+    if (hipHostMalloc((void **)&ctx->host_word, sizeof(int)) != hipSuccess) {
+      ctx->host_word = nullptr;
+      return fail(ctx, SS_ERR_NOMEM, "pinned host word allocation failed");
+    }
+  }
+  *out = ctx->host_word;
+  return SS_OK;
+}
+
+static hipEvent_t timer_event(ss_ctx *ctx) {
+  if (ctx->timer_used == ctx->timer_events.size()) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    ctx->timer_events.push_back(e);
+  }
+  return ctx->timer_events[ctx->timer_used++];
+}
+
+KernelScope::KernelScope(ss_ctx *c, const char *family) : ctx(c), on(false) {
+  if (!ctx->timer_family.empty() && ctx->timer_family == family) {
+    hipEvent_t e = timer_event(ctx);
+    if (e && hipEventRecord(e, ctx->stream) == hipSuccess) on = true;
+  }
+}
+
+KernelScope::~KernelScope() {
+  if (!on) return;
+  hipEvent_t e = timer_event(ctx);
+  if (!e || hipEventRecord(e, ctx->stream) != hipSuccess) {
+    ctx->timer_used -= e ? 2 : 1;  // drop the unmatched start event
+  }
+}
+
+static ss_status enter(ss_ctx *ctx) {
+  if (!ctx) return SS_ERR_ARG;
+  ctx->err.clear();
+  if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "hipSetDevice failed");
+  return SS_OK;
+}
+
+}  // namespace ss
+
+using namespace ss;
+
+extern "C" {
+
+const char *ss_status_string(ss_status st) {
+  switch (st) {
+    case SS_OK: return "ok";
+    case SS_ERR_ARG: return "invalid argument";
+    case SS_ERR_NOMEM: return "device allocation failed";
+    case SS_ERR_DEVICE: return "HIP runtime error";
+    case SS_ERR_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char *ss_last_error(const ss_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+ss_status ss_create(ss_ctx **out, int device, void *hip_stream) {
+  if (!out) return SS_ERR_ARG;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SS_ERR_ARG;
+  ss_ctx *ctx = new (std::nothrow) ss_ctx();
+  if (!ctx) return SS_ERR_NOMEM;
+  ctx->device = device;
+  ctx->stream = (hipStream_t)hip_stream;
+  *out = ctx;
+  return SS_OK;
+}
+
+void ss_destroy(ss_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  for (auto &b : ctx->slot)
+    if (b.ptr) (void)hipFree(b.ptr);
+  if (ctx->host_word) (void)hipHostFree(ctx->host_word);
+  for (hipEvent_t e : ctx->timer_events) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+ss_status ss_set_stream(ss_ctx *ctx, void *hip_stream) {
+  if (!ctx) return SS_ERR_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  return SS_OK;
+}
+
+ss_status ss_synchronize(ss_ctx *ctx) {
+  SS_TRY(enter(ctx));
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
+  return SS_OK;
+}
+
+size_t ss_workspace_bytes(const ss_ctx *ctx) {
+  if (!ctx) return 0;
+  size_t t = 0;
+  for (auto &b : ctx->slot) t += b.bytes;
+  return t;
+}
+
+ss_status ss_kernel_timer(ss_ctx *ctx, const char *family) {
+  SS_TRY(enter(ctx));
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
+  ctx->timer_family = family ? family : "";
+  ctx->timer_used = 0;
+  return SS_OK;
+}
+
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches) {
+  SS_TRY(enter(ctx));
+  if (!total_ms || !launches) return fail(ctx, SS_ERR_ARG, "ss_kernel_timer_read: null output");
+  if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
+  double t = 0.0;
+  const size_t pairs = ctx->timer_used / 2;
+  for (size_t i = 0; i < pairs; ++i) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ctx->timer_events[2 * i], ctx->timer_events[2 * i + 1]) != hipSuccess)
+      return fail(ctx, SS_ERR_DEVICE, "hipEventElapsedTime failed");
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (long long)pairs;
+  ctx->timer_used = 0;
+  return SS_OK;
+}
+
+ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
+                             const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E, double eta,
+                             double tol, int max_iter, ss_c128 *sigma, int *iters, double *resid, int *info) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || s < 1 || nk < 1) return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy: batch, s or nk out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_lead_selfenergy: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!H00 || !H01 || !S00 || !S01 || !E || !sigma)
+    return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy: null input or output pointer");
+  if (!(eta >= 0.0)) return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy: eta must be >= 0");
+  return lead_selfenergy(ctx, batch, s, nk, H00, H01, S00, S01, kidx, E, eta, tol, max_iter, sigma, iters, resid,
+                         info);
+}
+
+ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                                ss_c128 *Q, int *info) {
+  SS_TRY(enter(ctx));
+  if (!hs) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null structure");
+  if (batch < 0 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: batch, nb, s or nk out of range");
+  if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_precompute_columns: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!hs->H_diag || !hs->S_diag || !E || !Q || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)))
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null input or output pointer");
+  return precompute_columns(ctx, hs, batch, kidx, E, Q, info);
+}
+
+ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
+                       const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || nb < 1 || s < 1 || m < 0) return fail(ctx, SS_ERR_ARG, "ss_apply_obc: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_apply_obc: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!Q || !sigma || (m > 0 && (!inj || !psi)))
+    return fail(ctx, SS_ERR_ARG, "ss_apply_obc: null input or output pointer");
+  return apply_obc(ctx, batch, nb, s, Q, sigma, m, inj, psi, gc, info);
+}
+
+ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || s < 1) return fail(ctx, SS_ERR_ARG, "ss_transmission: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_transmission: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!gc || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission: null pointer");
+  return transmission(ctx, batch, s, gc, sigma, T);
+}
+
+}  // extern "C"

@@ -1,0 +1,105 @@
+// Shared host/device definitions of the SplitSolve HIP library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "splitsolve.h"
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ------------------------------------------------------------------ complex helpers (device)
+
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 cneg(double2 a) { return make_double2(-a.x, -a.y); }
+// a - b*c
+__device__ __forceinline__ double2 cfnms(double2 a, double2 b, double2 c) {
+  return make_double2(a.x - b.x * c.x + b.y * c.y, a.y - b.x * c.y - b.y * c.x);
+}
+// 1/u by scaling with the larger component (avoids overflow of |u|^2 for large entries)
+__device__ __forceinline__ double2 crecip(double2 u) {
+  if (fabs(u.x) >= fabs(u.y)) {
+    double r = u.y / u.x, d = u.x + u.y * r;
+    return make_double2(1.0 / d, -r / d);
+  } else {
+    double r = u.x / u.y, d = u.y + u.x * r;
+    return make_double2(r / d, -1.0 / d);
+  }
+}
+// component-wise copies (a plain double2 assignment between address spaces becomes a memcpy that
+// keeps register arrays out of registers)
+__device__ __forceinline__ void st2(double2 &dst, double2 v) { dst.x = v.x; dst.y = v.y; }
+__device__ __forceinline__ double2 ld2(const double2 &s) { return make_double2(s.x, s.y); }
+// LAPACK's pivot magnitude |Re| + |Im|
+__device__ __forceinline__ double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
+
+// ------------------------------------------------------------------ host side
+
+namespace ss {
+
+struct Buffer {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+enum Slot {
+  kSlotM = 0,      // augmented matrices of the batched LU solves
+  kSlotPerm,       // row permutations
+  kSlotTri,        // inverted diagonal blocks of L and U
+  kSlotZp,         // first zero pivot per factorization
+  kSlotX,          // per-step solutions of the recursion
+  kSlotInst,       // per-matrix instance tables
+  kSlotDec,        // decimation state
+  kSlotObc,        // corner system work
+  kSlotMisc,
+  kNumSlots
+};
+
+}  // namespace ss
+
+struct ss_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  ss::Buffer slot[ss::kNumSlots];
+  int *host_word = nullptr;  // pinned word for convergence polls
+  // kernel timing probe: launches of `timer_family` are bracketed by event pairs
+  std::string timer_family;
+  std::vector<hipEvent_t> timer_events;
+  size_t timer_used = 0;
+};
+
+namespace ss {
+
+// Grow-only device workspace; a reallocation waits for the stream so no queued kernel still uses it.
+ss_status workspace(ss_ctx *ctx, Slot s, size_t bytes, void **out);
+ss_status fail(ss_ctx *ctx, ss_status st, const std::string &msg);
+ss_status check_launch(ss_ctx *ctx, const char *what);
+ss_status host_word(ss_ctx *ctx, int **out);
+
+// Brackets the launches issued in its scope with a pair of events when `family` is being timed.
+struct KernelScope {
+  ss_ctx *ctx;
+  bool on;
+  KernelScope(ss_ctx *c, const char *family);
+  ~KernelScope();
+};
+
+__host__ __device__ inline int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+}  // namespace ss
+
+#define SS_TRY(expr)                  \
+  do {                                \
+    ss_status _st = (expr);           \
+    if (_st != SS_OK) return _st;     \
+  } while (0)

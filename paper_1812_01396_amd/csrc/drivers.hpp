@@ -1,0 +1,21 @@
+// Internal entry points behind the C ABI (argument checks happen in api.hip).
+#pragma once
+
+#include "common.hpp"
+
+namespace ss {
+
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                             ss_c128 *Q, int *info);
+
+ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
+                          const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
+                          double eta, double tol, int max_iter, ss_c128 *sigma, int *iters,
+                          double *resid, int *info);
+
+ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
+                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info);
+
+ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T);
+
+}  // namespace ss

@@ -1,0 +1,43 @@
+// Batched solve of dense complex systems D X = RHS by LU with partial pivoting (FP64).
+#pragma once
+
+#include "common.hpp"
+
+namespace ss {
+
+// Each of the nmat systems lives in an augmented row-major matrix [D | RHS] of n rows and
+// ldm >= n + nrhs columns.  Row interchanges are never performed in memory: the factorization keeps
+// a logical-to-physical row map `perm` instead, and every kernel addresses rows through it.  After
+// the call the physical rows hold L (unit lower, below the diagonal) and U of P D = L U, the RHS
+// columns hold L^{-1} P RHS, and X receives U^{-1} L^{-1} P RHS.
+struct LuDesc {
+  int nmat = 0, n = 0, nrhs = 0;
+  double2 *M = nullptr;
+  long sM = 0;
+  int ldm = 0;
+  int *perm = nullptr;  // [nmat][n]
+  long sP = 0;
+  double2 *tri = nullptr;  // [nmat][npanel][2][W][W]: inverses of the diagonal blocks of L and U
+  long sT = 0;
+  int *zp = nullptr;  // [nmat]: 1 + first column with an exactly zero pivot, 0 if none
+  double2 *X = nullptr;
+  long sX = 0;
+  int ldx = 0;
+  // optional: system i is skipped (every kernel returns at once) when skip[i >> skip_shift] != 0
+  const int *skip = nullptr;
+  int skip_shift = 0;
+};
+
+// Panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to 2048).
+int lu_panel_width(int n);
+// Elements (double2) of `tri` needed per system.
+long lu_tri_elems(int n);
+// Largest order supported.
+constexpr int kLuMaxN = 2048;
+
+// Enqueue the factorization and both triangular solves on ctx->stream.  The caller fills the
+// augmented matrices and sets perm to the identity (or lets `lu_identity_perm` do it).
+ss_status lu_solve(ss_ctx *ctx, const LuDesc &d);
+ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d);
+
+}  // namespace ss

@@ -1,0 +1,300 @@
+// Post-processing of SplitSolve (Sec. 3B, Eq. (x) and Steps 2-4) and the Caroli transmission.
+//
+// With B = [I 0 ... 0; 0 ... 0 I]^T (N x 2s), C = [Sigma_L 0 ...; ... 0 Sigma_R] (2s x N) and Q = A^{-1} B:
+//     C Q = [Sigma_L Q_{1,:}; Sigma_R Q_{nb,:}]                 (2s x 2s)
+//     R   = I - C Q,   [V | z] = R^{-1} [I | C Q b']           (one LU solve, 2s + m right-hand sides)
+//     gc  = [Q_{1,:}; Q_{nb,:}] V                               (corner of G^R = (A - B C)^{-1} = Q R^{-1})
+//     psi = Q (b' + z)                                          (y + Q z with y = Q b')
+// The transmission uses only the off-diagonal corner blocks:
+//     T_LR = Re Tr[Gamma_L G_1n Gamma_R G_1n^H] = Re sum_ij (Gamma_L G_1n)_ij conj((G_1n Gamma_R)_ij)
+// (Gamma Hermitian), and likewise T_RL with G_n1 and the leads exchanged.
+#include <algorithm>
+
+#include "drivers.hpp"
+#include "lu.hpp"
+#include "tile.hpp"
+
+namespace ss {
+
+using ObcTile = TileCfg<64, 64, 16, 2, 2>;
+
+// element (r, k) of Q_c = [Q_{1,:}; Q_{nb,:}] (2s x 2s) from Q [nb*s][2s]
+struct LdCorner {
+  const double2 *q;
+  int s, nb;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int k) const {
+    const long row = r < s ? r : (long)(nb - 1) * s + (r - s);
+    return q[row * 2 * s + k];
+  }
+};
+
+// element (k, c) of b' + z
+struct LdSum {
+  const double2 *b, *z;
+  long ldb, ldz;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int k, int c) const {
+    return cadd(b[(long)k * ldb + c], z[(long)k * ldz + c]);
+  }
+};
+
+// element (r, c) of Gamma = i (Sigma - Sigma^H)
+struct LdGamma {
+  const double2 *sig;
+  int s;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int c) const {
+    const double2 a = sig[(long)r * s + c], b = sig[(long)c * s + r];
+    // i * (a - conj(b)) = i*((a.x - b.x) + i (a.y + b.y)) = -(a.y + b.y) + i (a.x - b.x)
+    return make_double2(-(a.y + b.y), a.x - b.x);
+  }
+};
+
+struct ObcArgs {
+  const double2 *Q, *sigma, *inj;
+  double2 *psi, *gc;
+  int nb, s, m, batch;
+  double2 *M;   // [batch][2s][4s+m]
+  double2 *CQ;  // [batch][2s][2s]
+  double2 *X;   // [batch][2s][2s+m]
+};
+
+// C Q, R = I - C Q and the identity block: grid (2 halves * tiles(s) * tiles(2s), batch)
+__global__ void __launch_bounds__(ObcTile::NT) k_obc_cq(ObcArgs a) {
+  using T = ObcTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int inst = blockIdx.y, s = a.s, nb = a.nb;
+  const int tr = cdiv(s, T::BM), tc = cdiv(2 * s, T::BN);
+  int t = blockIdx.x;
+  const int half = t / (tr * tc);
+  t %= tr * tc;
+  const int m0 = (t / tc) * T::BM, n0 = (t % tc) * T::BN;
+  const long ss2 = (long)s * s;
+  const double2 *sig = a.sigma + ((long)inst * 2 + half) * ss2;  // half 0: Sigma_L, 1: Sigma_R
+  const double2 *qrow = a.Q + (long)inst * nb * 2 * ss2 + (half ? (long)(nb - 1) * 2 * ss2 : 0);
+  Acc<T> acc;
+  acc.zero();
+  LdRow la{sig, s};
+  LdRow lb{qrow, 2 * s};
+  mma_loop<T>(la, lb, m0, s, n0, 2 * s, 0, s, acc, lds);
+  const int ldm = 4 * s + a.m;
+  double2 *M = a.M + (long)inst * 2 * s * ldm;
+  double2 *cq = a.CQ + (long)inst * 4 * ss2;
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < s && gc < 2 * s) {
+      const int row = half * s + gr;
+      const double d = row == gc ? 1.0 : 0.0;
+      cq[(long)row * 2 * s + gc] = v;
+      M[(long)row * ldm + gc] = make_double2(d - v.x, -v.y);
+      M[(long)row * ldm + 2 * s + gc] = make_double2(d, 0.0);
+    }
+  });
+}
+
+// C Q b' into the last m columns of the augmented matrix
+__global__ void __launch_bounds__(ObcTile::NT) k_obc_cqb(ObcArgs a) {
+  using T = ObcTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int inst = blockIdx.y, s = a.s, m = a.m;
+  const int tc = cdiv(m, T::BN);
+  const int m0 = (blockIdx.x / tc) * T::BM, n0 = (blockIdx.x % tc) * T::BN;
+  Acc<T> acc;
+  acc.zero();
+  LdRow la{a.CQ + (long)inst * 4 * s * s, 2 * s};
+  LdRow lb{a.inj + (long)inst * 2 * s * m, m};
+  mma_loop<T>(la, lb, m0, 2 * s, n0, m, 0, 2 * s, acc, lds);
+  const int ldm = 4 * s + m;
+  double2 *M = a.M + (long)inst * 2 * s * ldm;
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < 2 * s && gc < m) M[(long)gr * ldm + 4 * s + gc] = v;
+  });
+}
+
+// gc = Q_c V
+__global__ void __launch_bounds__(ObcTile::NT) k_obc_gc(ObcArgs a) {
+  using T = ObcTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int inst = blockIdx.y, s = a.s;
+  const int tc = cdiv(2 * s, T::BN);
+  const int m0 = (blockIdx.x / tc) * T::BM, n0 = (blockIdx.x % tc) * T::BN;
+  const int ldx = 2 * s + a.m;
+  Acc<T> acc;
+  acc.zero();
+  LdCorner la{a.Q + (long)inst * a.nb * 2 * s * s, s, a.nb};
+  LdRow lb{a.X + (long)inst * 2 * s * ldx, ldx};
+  mma_loop<T>(la, lb, m0, 2 * s, n0, 2 * s, 0, 2 * s, acc, lds);
+  double2 *g = a.gc + (long)inst * 4 * s * s;
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    const int gr = m0 + r, gcl = n0 + c;
+    if (gr < 2 * s && gcl < 2 * s) g[(long)gr * 2 * s + gcl] = v;
+  });
+}
+
+// psi = Q (b' + z): rows nb*s, columns m, depth 2s
+__global__ void __launch_bounds__(ObcTile::NT) k_obc_psi(ObcArgs a) {
+  using T = ObcTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int inst = blockIdx.y, s = a.s, m = a.m;
+  const int rows = a.nb * s;
+  const int tc = cdiv(m, T::BN);
+  const int m0 = (blockIdx.x / tc) * T::BM, n0 = (blockIdx.x % tc) * T::BN;
+  const int ldx = 2 * s + m;
+  Acc<T> acc;
+  acc.zero();
+  LdRow la{a.Q + (long)inst * rows * 2 * s, 2 * s};
+  LdSum lb{a.inj + (long)inst * 2 * s * m, a.X + (long)inst * 2 * s * ldx + 2 * s, m, ldx};
+  mma_loop<T>(la, lb, m0, rows, n0, m, 0, 2 * s, acc, lds);
+  double2 *p = a.psi + (long)inst * rows * m;
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < rows && gc < m) p[(long)gr * m + gc] = v;
+  });
+}
+
+__global__ void k_obc_info(const int *zp, int *info, int batch) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < batch && info) info[i] = zp[i];
+}
+
+ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
+                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+  const long ss2 = (long)s * s;
+  const int n = 2 * s, nrhs = 2 * s + m, ldm = 4 * s + m;
+  void *wM, *wP, *wT, *wZ, *wO;
+  SS_TRY(workspace(ctx, kSlotM, sizeof(double2) * (size_t)batch * n * ldm, &wM));
+  SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * (size_t)batch * n, &wP));
+  SS_TRY(workspace(ctx, kSlotTri, sizeof(double2) * (size_t)batch * lu_tri_elems(n), &wT));
+  SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)batch, &wZ));
+  SS_TRY(workspace(ctx, kSlotObc, sizeof(double2) * (size_t)batch * (4 * ss2 + (long)n * nrhs), &wO));
+  ObcArgs a;
+  a.Q = (const double2 *)Q;
+  a.sigma = (const double2 *)sigma;
+  a.inj = (const double2 *)inj;
+  a.psi = (double2 *)psi;
+  a.gc = (double2 *)gc;
+  a.nb = nb;
+  a.s = s;
+  a.m = m;
+  a.batch = batch;
+  a.M = (double2 *)wM;
+  a.CQ = (double2 *)wO;
+  a.X = a.CQ + (size_t)batch * 4 * ss2;
+
+  using T = ObcTile;
+  const int tr = cdiv(s, T::BM), tc2 = cdiv(2 * s, T::BN);
+  {
+    KernelScope ks_(ctx, "obc");
+    hipLaunchKernelGGL(k_obc_cq, dim3(2 * tr * tc2, batch), dim3(T::NT), 0, ctx->stream, a);
+  }
+  if (m > 0)
+    {
+      KernelScope ks_(ctx, "obc");
+      hipLaunchKernelGGL(k_obc_cqb, dim3(cdiv(2 * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0, ctx->stream,
+                         a);
+    }
+  LuDesc d;
+  d.nmat = batch;
+  d.n = n;
+  d.nrhs = nrhs;
+  d.M = a.M;
+  d.sM = (long)n * ldm;
+  d.ldm = ldm;
+  d.perm = (int *)wP;
+  d.sP = n;
+  d.tri = (double2 *)wT;
+  d.sT = lu_tri_elems(n);
+  d.zp = (int *)wZ;
+  d.X = a.X;
+  d.sX = (long)n * nrhs;
+  d.ldx = nrhs;
+  SS_TRY(lu_identity_perm(ctx, d));
+  SS_TRY(lu_solve(ctx, d));
+  if (gc)
+    {
+      KernelScope ks_(ctx, "obc");
+      hipLaunchKernelGGL(k_obc_gc, dim3(cdiv(2 * s, T::BM) * tc2, batch), dim3(T::NT), 0, ctx->stream, a);
+    }
+  if (m > 0 && psi)
+    {
+      KernelScope ks_(ctx, "obc");
+      hipLaunchKernelGGL(k_obc_psi, dim3(cdiv(nb * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0,
+                         ctx->stream, a);
+    }
+  hipLaunchKernelGGL(k_obc_info, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const int *)wZ, info, batch);
+  return check_launch(ctx, "apply_obc");
+}
+
+// ------------------------------------------------------------------ transmission
+
+using TrTile = TileCfg<32, 32, 16, 2, 2>;
+
+// per (instance, direction, tile): partial sum of Re[(Gam_a G)_ij conj((G Gam_b)_ij)]
+__global__ void __launch_bounds__(TrTile::NT) k_trans(const double2 *gcp, const double2 *sigma, int s,
+                                                       double *partial) {
+  using T = TrTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  __shared__ double red[T::NT / 64];
+  const int inst = blockIdx.z, dir = blockIdx.y;  // dir 0: T_LR with G_1n; dir 1: T_RL with G_n1
+  const int tiles = cdiv(s, T::BM);
+  const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
+  const long ss2 = (long)s * s;
+  const double2 *g = gcp + (long)inst * 4 * ss2 + (dir == 0 ? s : (long)s * 2 * s);  // G_1n or G_n1
+  const double2 *sig_a = sigma + ((long)inst * 2 + (dir == 0 ? 0 : 1)) * ss2;  // left factor's lead
+  const double2 *sig_b = sigma + ((long)inst * 2 + (dir == 0 ? 1 : 0)) * ss2;
+  Acc<T> p1, p2;
+  p1.zero();
+  p2.zero();
+  LdGamma ga{sig_a, s}, gb{sig_b, s};
+  LdRow lg{g, 2 * s};
+  mma_loop<T>(ga, lg, m0, s, n0, s, 0, s, p1, lds);
+  mma_loop<T>(lg, gb, m0, s, n0, s, 0, s, p2, lds);
+  double acc = 0.0;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = m0 + wm * T::FM * 16 + i * 16 + 4 * q + (lane >> 4);
+        const int c = n0 + wn * T::FN * 16 + j * 16 + (lane & 15);
+        if (r < s && c < s) acc += p1.re[i][j][q] * p2.re[i][j][q] + p1.im[i][j][q] * p2.im[i][j][q];
+      }
+  for (int off = 32; off >= 1; off >>= 1) acc += __shfl_xor(acc, off);
+  if (lane == 0) red[wave] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < T::NT / 64; ++w) t += red[w];
+    partial[((long)inst * 2 + dir) * gridDim.x + blockIdx.x] = t;
+  }
+}
+
+__global__ void k_trans_sum(const double *partial, int ntile, double *T, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0;
+  for (int k = 0; k < ntile; ++k) t += partial[(long)i * ntile + k];
+  T[i] = t;
+}
+
+ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
+  const int tiles = cdiv(s, TrTile::BM);
+  const int ntile = tiles * tiles;
+  void *wP;
+  SS_TRY(workspace(ctx, kSlotMisc, sizeof(double) * (size_t)batch * 2 * ntile, &wP));
+  {
+    KernelScope ks_(ctx, "trans");
+    hipLaunchKernelGGL(k_trans, dim3(ntile, 2, batch), dim3(TrTile::NT), 0, ctx->stream, (const double2 *)gc,
+                       (const double2 *)sigma, s, (double *)wP);
+  }
+  hipLaunchKernelGGL(k_trans_sum, dim3(cdiv(2 * batch, 256)), dim3(256), 0, ctx->stream, (const double *)wP, ntile,
+                     T, 2 * batch);
+  return check_launch(ctx, "transmission");
+}
+
+}  // namespace ss

@@ -1,0 +1,248 @@
+// Step 1 of SplitSolve (Sec. 3B, Alg. 1): first and last block columns Q of A^{-1}, A = E*S - H.
+//
+// Every instance runs two independent recursions ("directions") in lockstep, as separate systems of
+// one batch:
+//   direction 0 (first column), 0-based block ib = nb-1-t at step t:
+//     D = A_{ib,ib} - A_{ib,ib+1} X_{ib+1},   X_{ib} = D^{-1} A_{ib,ib-1},   A_{0,-1} := I
+//   direction 1 (last column), block ib = t:
+//     D = A_{ib,ib} - A_{ib,ib-1} Y_{ib-1},   Y_{ib} = D^{-1} A_{ib,ib+1},   A_{nb-1,nb} := I
+// A is never stored: its blocks are formed as E*S - H inside the tile loads.  The per-step
+// solutions go to slot t of a per-system store, so both directions address slot t at step t.
+// Then the chains Q_{ib} = -X_{ib} Q_{ib-1} (from Q_0 = X_0) and Q'_{ib} = -Y_{ib} Q'_{ib+1} (from
+// Q'_{nb-1} = Y_{nb-1}) both read slot nb-1-u at chain step u and write into the caller's Q.
+#include <algorithm>
+#include <climits>
+
+#include "lu.hpp"
+#include "drivers.hpp"
+#include "tile.hpp"
+
+namespace ss {
+
+struct SweepArgs {
+  const double2 *Hd, *Hu, *Sd, *Su;
+  long kstride_d, kstride_u;  // elements between consecutive (H, S) sets
+  const int *kidx;
+  const double *E;
+  int nk, nb, s;
+  double2 *M;  // [nmat][s][2s]
+  int *perm;   // [nmat][s]
+  int *zp;     // [nmat]
+  int *code;   // [batch] smallest zero-pivot code, INT_MAX if none
+  double2 *X;  // [nmat][nb][s][s]
+  double2 *Q;  // [batch][nb][s][2s]
+  int *info;   // [batch] or null
+  int batch;
+};
+
+// (H, S) set of an instance; out-of-range indices are clamped so a bad index cannot address
+// outside the caller's arrays (the binding rejects them before the call).
+__device__ __forceinline__ int set_of(const SweepArgs &a, int inst) {
+  const int k = a.kidx ? a.kidx[inst] : inst % a.nk;
+  return min(max(k, 0), a.nk - 1);
+}
+
+using FormTile = TileCfg<64, 64, 16, 2, 2>;
+
+// Forms [D | RHS] of step t for every system; fold the previous step's zero pivot into `code`.
+__global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
+  using T = FormTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
+  const int s = a.s, nb = a.nb;
+  const int ks = set_of(a, inst);
+  const double e = a.E[inst];
+  const int ib = dir == 0 ? nb - 1 - t : t;
+  const long ss2 = (long)s * s;
+  const double2 *hd = a.Hd + ks * a.kstride_d + ib * ss2;
+  const double2 *sd = a.Sd + ks * a.kstride_d + ib * ss2;
+  double2 *M = a.M + (long)mat * 2 * ss2;
+  const int tiles = cdiv(s, T::BM);
+  const int ntile = tiles * tiles;
+  int tile = blockIdx.x;
+
+  if (tile == 0 && threadIdx.x == 0 && t > 0) {
+    const int z = a.zp[mat];
+    if (z != 0) {
+      const int pib = dir == 0 ? nb - t : t - 1;  // block of the previous step
+      atomicMin(a.code + inst, pib * s + z);
+    }
+  }
+
+  if (tile < ntile) {
+    // D tile: D = A_ib,ib - coupling * previous solution
+    const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
+    Acc<T> acc;
+    acc.zero();
+    const bool has_prev = t > 0;
+    if (has_prev) {
+      const double2 *xp = a.X + ((long)mat * nb + (t - 1)) * ss2;
+      LdRow lb{xp, s};
+      if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
+        LdForm<false> la{a.Hu + ks * a.kstride_u + ib * ss2, a.Su + ks * a.kstride_u + ib * ss2, s, e};
+        mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
+      } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
+        LdForm<true> la{a.Hu + ks * a.kstride_u + (ib - 1) * ss2, a.Su + ks * a.kstride_u + (ib - 1) * ss2,
+                        s, e};
+        mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
+      }
+    }
+    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+      const int gr = m0 + r, gc = n0 + c;
+      if (gr < s && gc < s) {
+        const long o = (long)gr * s + gc;
+        const double2 av = make_double2(e * sd[o].x - hd[o].x, e * sd[o].y - hd[o].y);
+        M[(long)gr * 2 * s + gc] = csub(av, v);
+      }
+    });
+    if (n0 == 0) {
+      for (int r = threadIdx.x; r < T::BM; r += T::NT)
+        if (m0 + r < s) a.perm[(long)mat * s + m0 + r] = m0 + r;
+    }
+  } else {
+    // RHS tile: the coupling to the already-eliminated side, or the identity at the boundary
+    tile -= ntile;
+    const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
+    const bool ident = dir == 0 ? ib == 0 : ib == nb - 1;
+    const int ub = dir == 0 ? ib - 1 : ib;
+    const double2 *hu = a.Hu + ks * a.kstride_u + (long)std::max(ub, 0) * ss2;
+    const double2 *su = a.Su + ks * a.kstride_u + (long)std::max(ub, 0) * ss2;
+    for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
+      const int r = idx / T::BN, c = idx % T::BN;
+      const int gr = m0 + r, gc = n0 + c;
+      if (gr >= s || gc >= s) continue;
+      double2 v;
+      if (ident) v = make_double2(gr == gc ? 1.0 : 0.0, 0.0);
+      else if (dir == 0) {  // (E S_u - H_u)^H element (gr, gc) = conj(E S_u[gc][gr] - H_u[gc][gr])
+        const long o = (long)gc * s + gr;
+        v = make_double2(e * su[o].x - hu[o].x, -(e * su[o].y - hu[o].y));
+      } else {
+        const long o = (long)gr * s + gc;
+        v = make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
+      }
+      M[(long)gr * 2 * s + s + gc] = v;
+    }
+  }
+}
+
+// Fold the last step's zero pivot and publish info.
+__global__ void k_sweep_finish(SweepArgs a) {
+  const int inst = blockIdx.x * blockDim.x + threadIdx.x;
+  if (inst >= a.batch) return;
+  int c = a.code[inst];
+  for (int dir = 0; dir < 2; ++dir) {
+    const int z = a.zp[2 * inst + dir];
+    if (z != 0) {
+      const int pib = dir == 0 ? 0 : a.nb - 1;
+      c = min(c, pib * a.s + z);
+    }
+  }
+  if (a.info) a.info[inst] = c == INT_MAX ? 0 : c;
+}
+
+__global__ void k_code_init(int *code, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) code[i] = INT_MAX;
+}
+
+// Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
+__global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
+  using T = FormTile;
+  __shared__ double lds[T::LDS_DOUBLES];
+  const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
+  const int s = a.s, nb = a.nb;
+  const long ss2 = (long)s * s;
+  const int tiles = cdiv(s, T::BM);
+  const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
+  const int ib = dir == 0 ? u : nb - 1 - u;
+  const double2 *x = a.X + ((long)mat * nb + (nb - 1 - u)) * ss2;
+  double2 *qi = a.Q + (long)inst * nb * 2 * ss2 + (long)ib * 2 * ss2 + (dir ? s : 0);
+  if (u == 0) {
+    for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
+      const int gr = m0 + idx / T::BN, gc = n0 + idx % T::BN;
+      if (gr < s && gc < s) qi[(long)gr * 2 * s + gc] = x[(long)gr * s + gc];
+    }
+    return;
+  }
+  const int pb = dir == 0 ? ib - 1 : ib + 1;
+  const double2 *qp = a.Q + (long)inst * nb * 2 * ss2 + (long)pb * 2 * ss2 + (dir ? s : 0);
+  Acc<T> acc;
+  acc.zero();
+  LdRow la{x, s};
+  LdRow lb{qp, 2 * s};
+  mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < s && gc < s) qi[(long)gr * 2 * s + gc] = cneg(v);
+  });
+}
+
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                             ss_c128 *Q, int *info) {
+  const int s = hs->s, nb = hs->nb, nmat = 2 * batch;
+  const long ss2 = (long)s * s;
+  const int n = s, nrhs = s, ldm = 2 * s;
+  void *wM, *wP, *wT, *wZ, *wX, *wC;
+  SS_TRY(workspace(ctx, kSlotM, sizeof(double2) * nmat * (size_t)n * ldm, &wM));
+  SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * nmat * (size_t)n, &wP));
+  SS_TRY(workspace(ctx, kSlotTri, sizeof(double2) * nmat * (size_t)lu_tri_elems(n), &wT));
+  SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)(nmat + batch), &wZ));
+  SS_TRY(workspace(ctx, kSlotX, sizeof(double2) * nmat * (size_t)nb * ss2, &wX));
+  wC = (int *)wZ + nmat;
+
+  SweepArgs a;
+  a.Hd = (const double2 *)hs->H_diag;
+  a.Hu = (const double2 *)hs->H_upper;
+  a.Sd = (const double2 *)hs->S_diag;
+  a.Su = (const double2 *)hs->S_upper;
+  a.kstride_d = (long)nb * ss2;
+  a.kstride_u = (long)std::max(nb - 1, 0) * ss2;
+  a.kidx = kidx;
+  a.E = E;
+  a.nk = hs->nk;
+  a.nb = nb;
+  a.s = s;
+  a.M = (double2 *)wM;
+  a.perm = (int *)wP;
+  a.zp = (int *)wZ;
+  a.code = (int *)wC;
+  a.X = (double2 *)wX;
+  a.Q = (double2 *)Q;
+  a.info = info;
+  a.batch = batch;
+
+  LuDesc d;
+  d.nmat = nmat;
+  d.n = n;
+  d.nrhs = nrhs;
+  d.M = a.M;
+  d.sM = (long)n * ldm;
+  d.ldm = ldm;
+  d.perm = a.perm;
+  d.sP = n;
+  d.tri = (double2 *)wT;
+  d.sT = lu_tri_elems(n);
+  d.zp = a.zp;
+  d.sX = (long)nb * ss2;
+  d.ldx = s;
+
+  hipLaunchKernelGGL(k_code_init, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a.code, batch);
+  const int tiles = cdiv(s, FormTile::BM);
+  for (int t = 0; t < nb; ++t) {
+    {
+      KernelScope ks_(ctx, "form");
+      hipLaunchKernelGGL(k_form, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
+    }
+    d.X = a.X + (long)t * ss2;
+    SS_TRY(lu_solve(ctx, d));
+  }
+  hipLaunchKernelGGL(k_sweep_finish, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a);
+  for (int u = 0; u < nb; ++u)
+    {
+      KernelScope ks_(ctx, "chain");
+      hipLaunchKernelGGL(k_chain, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
+    }
+  return check_launch(ctx, "precompute_columns");
+}
+
+}  // namespace ss

@@ -1,0 +1,278 @@
+// Complex FP64 tile engine on the gfx950 matrix cores (v_mfma_f64_16x16x4_f64).
+//
+// A workgroup of WM x WN wavefronts computes a BM x BN tile of complex outputs
+//     acc(r, c) = sum_k A(r, k) * B(k, c)
+// with A and B fetched through loader functors (plain row-major, row-permuted, conjugate-transposed,
+// or formed on the fly as E*S - H).  Operands are staged through LDS as separate real and imaginary
+// planes laid out [k][m] and [k][n], so each MFMA operand read is 16 consecutive doubles per k row.
+// A complex product is four real MFMAs (re*re - im*im, re*im + im*re); the next stage's global loads
+// are issued before the current stage's MFMAs so their latency hides behind the matrix work.
+//
+// Register layout of v_mfma_f64_16x16x4_f64 (wave64), measured on gfx950:
+//   A (16x4):  lane l holds A[l % 16][l / 16]
+//   B (4x16):  lane l holds B[l / 16][l % 16]
+//   D (16x16): lane l, element j holds D[4*j + l / 16][l % 16]
+#pragma once
+
+#include "common.hpp"
+
+namespace ss {
+
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct TileCfg {
+  static constexpr int BM = BM_, BN = BN_, BK = BK_, WM = WM_, WN = WN_;
+  static constexpr int NT = 64 * WM * WN;
+  static constexpr int FM = BM / (16 * WM);
+  static constexpr int FN = BN / (16 * WN);
+  static constexpr int PA = BM + 1;  // odd row pitch (doubles): conflict-free transposing stores
+  static constexpr int PB = BN + 1;
+  static constexpr int LDS_DOUBLES = 2 * BK * PA + 2 * BK * PB;
+  static constexpr int EA = (BM * BK + NT - 1) / NT;
+  static constexpr int EB = (BK * BN + NT - 1) / NT;
+  static_assert(FM >= 1 && FN >= 1, "tile smaller than one MFMA block per wave");
+  static_assert(FM * 16 * WM == BM && FN * 16 * WN == BN, "tile not a multiple of the wave grid");
+  static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA depth");
+};
+
+template <class T>
+struct Acc {
+  v4d re[T::FM][T::FN];
+  v4d im[T::FM][T::FN];
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j) {
+        re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+        im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+      }
+  }
+};
+
+// ------------------------------------------------------------------ loaders
+// A loader returns element (r, k) of the left operand, a B loader element (k, c) of the right one.
+// kFastSecond: consecutive values of the second index are contiguous in memory (row-major).
+
+struct LdRow {  // p[r * ld + c]
+  const double2 *p;
+  long ld;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int c) const { return p[(long)r * ld + c]; }
+};
+
+struct LdRowPerm {  // p[perm[r] * ld + c]; perm usually lives in LDS
+  const double2 *p;
+  long ld;
+  const int *perm;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int c) const { return p[(long)perm[r] * ld + c]; }
+};
+
+// element (r, c) of E*S - H (kConj == false) or of (E*S - H)^H (kConj == true) for row-major
+// blocks H, S with leading dimension ld; E is real.
+template <bool kConj>
+struct LdForm {
+  const double2 *h, *s;
+  long ld;
+  double e;
+  static constexpr bool kFastSecond = !kConj;
+  __device__ __forceinline__ double2 operator()(int r, int c) const {
+    long o = kConj ? (long)c * ld + r : (long)r * ld + c;
+    double2 hv = h[o], sv = s[o];
+    double2 v = make_double2(e * sv.x - hv.x, e * sv.y - hv.y);
+    return kConj ? cconj(v) : v;
+  }
+};
+
+// ------------------------------------------------------------------ engine
+
+template <class T>
+struct Lds {
+  double *ar, *ai, *br, *bi;
+  __device__ __forceinline__ explicit Lds(double *base) {
+    ar = base;
+    ai = ar + T::BK * T::PA;
+    br = ai + T::BK * T::PA;
+    bi = br + T::BK * T::PB;
+  }
+};
+
+// One BK-deep stage of MFMAs from LDS into the accumulators.
+template <class T, int KSTEPS = T::BK / 4>
+__device__ __forceinline__ void mma_stage(const Lds<T> &L, Acc<T> &acc) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+  const int mbase = wm * T::FM * 16 + (lane & 15);
+  const int nbase = wn * T::FN * 16 + (lane & 15);
+#pragma unroll
+  for (int ks = 0; ks < KSTEPS; ++ks) {
+    const int kr = ks * 4 + (lane >> 4);
+    double ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i) {
+      ar[i] = L.ar[kr * T::PA + mbase + i * 16];
+      ai[i] = L.ai[kr * T::PA + mbase + i * 16];
+      an[i] = -ai[i];
+    }
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) {
+      br[j] = L.br[kr * T::PB + nbase + j * 16];
+      bi[j] = L.bi[kr * T::PB + nbase + j * 16];
+    }
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j) {
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], acc.re[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+      }
+  }
+}
+
+// acc += A[m0:m0+BM, kbeg:kend] * B[kbeg:kend, n0:n0+BN]; rows >= M and columns >= N read as zero.
+// All threads of the workgroup must call this (it synchronizes).  `lds` holds T::LDS_DOUBLES.
+template <class T, class LA, class LB>
+__device__ __forceinline__ void mma_loop(const LA &la, const LB &lb, int m0, int M, int n0, int N,
+                                         int kbeg, int kend, Acc<T> &acc, double *lds) {
+  if (kbeg >= kend) return;
+  const int tid = threadIdx.x;
+  Lds<T> L(lds);
+  double2 ra[T::EA], rb[T::EB];
+  auto gload = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const int idx = tid + e * T::NT;
+      int r, k;
+      if (LA::kFastSecond) { r = idx / T::BK; k = idx % T::BK; }
+      else { r = idx % T::BM; k = idx / T::BM; }
+      const bool ok = (idx < T::BM * T::BK) && (m0 + r < M) && (k0 + k < kend);
+      ra[e] = ok ? la(m0 + r, k0 + k) : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const int idx = tid + e * T::NT;
+      int k, c;
+      if (LB::kFastSecond) { k = idx / T::BN; c = idx % T::BN; }
+      else { k = idx % T::BK; c = idx / T::BK; }
+      const bool ok = (idx < T::BK * T::BN) && (n0 + c < N) && (k0 + k < kend);
+      rb[e] = ok ? lb(k0 + k, n0 + c) : make_double2(0.0, 0.0);
+    }
+  };
+  auto sstore = [&]() {
+#pragma unroll
+    for (int e = 0; e < T::EA; ++e) {
+      const int idx = tid + e * T::NT;
+      if (idx < T::BM * T::BK) {
+        int r, k;
+        if (LA::kFastSecond) { r = idx / T::BK; k = idx % T::BK; }
+        else { r = idx % T::BM; k = idx / T::BM; }
+        L.ar[k * T::PA + r] = ra[e].x;
+        L.ai[k * T::PA + r] = ra[e].y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < T::EB; ++e) {
+      const int idx = tid + e * T::NT;
+      if (idx < T::BK * T::BN) {
+        int k, c;
+        if (LB::kFastSecond) { k = idx / T::BN; c = idx % T::BN; }
+        else { k = idx % T::BK; c = idx / T::BK; }
+        L.br[k * T::PB + c] = rb[e].x;
+        L.bi[k * T::PB + c] = rb[e].y;
+      }
+    }
+  };
+  gload(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += T::BK) {
+    __syncthreads();  // the previous stage's MFMAs have read their operands
+    sstore();
+    __syncthreads();
+    if (k0 + T::BK < kend) gload(k0 + T::BK);
+    mma_stage<T>(L, acc);
+  }
+}
+
+// Visit every accumulator element with its (row, col) inside the BM x BN tile.
+template <class T, class F>
+__device__ __forceinline__ void acc_foreach(const Acc<T> &acc, F &&f) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+#pragma unroll
+  for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = wm * T::FM * 16 + i * 16 + 4 * q + (lane >> 4);
+        const int c = wn * T::FN * 16 + j * 16 + (lane & 15);
+        f(r, c, make_double2(acc.re[i][j][q], acc.im[i][j][q]));
+      }
+}
+
+// Second product inside the tile: out = Tri * C where Tri is a K x K block (K <= BM, given as a
+// loader over [0, K) x [0, K)) and C is the BM x BN tile held in `acc`, transformed element-wise by
+// `pre(r, c, v)` before the product.  Used to apply an inverted triangular diagonal block to the
+// rows of a tile.  Result returned in `acc` (rows >= K are zero).
+template <class T, class LT, class Pre>
+__device__ __forceinline__ void tri_apply(const LT &tri, int K, Acc<T> &acc, Pre &&pre, double *lds) {
+  static_assert(T::BK >= 4, "");
+  Lds<T> L(lds);
+  // stage the tile as the B operand [k = tile row][n = tile col]; needs BM rows of B planes
+  // (the engine's B planes hold BK rows; use the A planes' storage for the overflow when BM > BK)
+  double *cr = lds;                        // [BM][PB]
+  double *ci = lds + T::BM * T::PB;        // [BM][PB]
+  double *tr = ci + T::BM * T::PB;         // [BM][PA]  tri^T planes: tr[k][m] = tri(m, k)
+  double *ti = tr + T::BM * T::PA;
+  __syncthreads();
+  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    double2 w = pre(r, c, v);
+    cr[r * T::PB + c] = w.x;
+    ci[r * T::PB + c] = w.y;
+  });
+  for (int idx = threadIdx.x; idx < T::BM * T::BM; idx += T::NT) {
+    const int m = idx / T::BM, k = idx % T::BM;
+    double2 v = (m < K && k < K) ? tri(m, k) : make_double2(0.0, 0.0);
+    tr[k * T::PA + m] = v.x;
+    ti[k * T::PA + m] = v.y;
+  }
+  __syncthreads();
+  acc.zero();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave % T::WM, wn = wave / T::WM;
+  const int mbase = wm * T::FM * 16 + (lane & 15);
+  const int nbase = wn * T::FN * 16 + (lane & 15);
+  for (int ks = 0; ks < T::BM / 4; ++ks) {
+    const int kr = ks * 4 + (lane >> 4);
+    double ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i) {
+      ar[i] = tr[kr * T::PA + mbase + i * 16];
+      ai[i] = ti[kr * T::PA + mbase + i * 16];
+      an[i] = -ai[i];
+    }
+#pragma unroll
+    for (int j = 0; j < T::FN; ++j) {
+      br[j] = cr[kr * T::PB + nbase + j * 16];
+      bi[j] = ci[kr * T::PB + nbase + j * 16];
+    }
+#pragma unroll
+    for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j) {
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
+        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], acc.re[i][j], 0, 0, 0);
+        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+      }
+  }
+  (void)L;
+}
+
+template <class T>
+constexpr int tri_lds_doubles() {
+  return 2 * T::BM * T::PB + 2 * T::BM * T::PA;
+}
+
+}  // namespace ss

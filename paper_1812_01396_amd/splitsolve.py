@@ -1,0 +1,250 @@
+"""Python binding of the SplitSolve C ABI (include/splitsolve.h) through ctypes.
+
+Argument marshalling only: every step of the computation runs in the HIP library
+``libsplitsolve.so``.  PyTorch supplies device memory and the stream; tensors must live on the
+context's GPU, be contiguous, and use complex128 (matrices), float64 (energies) or int32 (indices).
+If the library is missing, importing works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsplitsolve.so")
+
+SS_OK, SS_ERR_ARG, SS_ERR_NOMEM, SS_ERR_DEVICE, SS_ERR_UNSUPPORTED = range(5)
+SS_MAX_S = 1024
+
+EXPORTS = (
+    "ss_create", "ss_destroy", "ss_set_stream", "ss_synchronize", "ss_status_string", "ss_last_error",
+    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy", "ss_precompute_columns", "ss_apply_obc", "ss_transmission",
+)
+
+
+class SplitSolveError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"status {status}: {msg}")
+        self.status = status
+
+
+class _Btd(ctypes.Structure):
+    _fields_ = [
+        ("nb", ctypes.c_int), ("s", ctypes.c_int), ("nk", ctypes.c_int),
+        ("H_diag", ctypes.c_void_p), ("H_upper", ctypes.c_void_p),
+        ("S_diag", ctypes.c_void_p), ("S_upper", ctypes.c_void_p),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsplitsolve.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} is missing "
+                           "(run `python -m paper_1812_01396_amd.build`)")
+    lib = ctypes.CDLL(path)
+    P, I, D, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_size_t
+    lib.ss_create.argtypes = [ctypes.POINTER(P), I, P]
+    lib.ss_create.restype = I
+    lib.ss_destroy.argtypes = [P]
+    lib.ss_destroy.restype = None
+    lib.ss_set_stream.argtypes = [P, P]
+    lib.ss_set_stream.restype = I
+    lib.ss_synchronize.argtypes = [P]
+    lib.ss_synchronize.restype = I
+    lib.ss_status_string.argtypes = [I]
+    lib.ss_status_string.restype = ctypes.c_char_p
+    lib.ss_last_error.argtypes = [P]
+    lib.ss_last_error.restype = ctypes.c_char_p
+    lib.ss_workspace_bytes.argtypes = [P]
+    lib.ss_workspace_bytes.restype = Z
+    lib.ss_kernel_timer.argtypes = [P, ctypes.c_char_p]
+    lib.ss_kernel_timer.restype = I
+    lib.ss_kernel_timer_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong)]
+    lib.ss_kernel_timer_read.restype = I
+    lib.ss_lead_selfenergy.argtypes = [P, I, I, I, P, P, P, P, P, P, D, D, I, P, P, P, P]
+    lib.ss_lead_selfenergy.restype = I
+    lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, P, P]
+    lib.ss_precompute_columns.restype = I
+    lib.ss_apply_obc.argtypes = [P, I, I, I, P, P, I, P, P, P, P]
+    lib.ss_apply_obc.restype = I
+    lib.ss_transmission.argtypes = [P, I, I, P, P, P]
+    lib.ss_transmission.restype = I
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _check_kidx(kidx, nk):
+    if kidx.numel() and (int(kidx.min()) < 0 or int(kidx.max()) >= nk):
+        raise ValueError(f"kidx entries must lie in [0, {nk})")
+
+
+def _need(t, dtype, device, name, shape=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name}: expected a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name}: expected {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name}: expected a tensor on {device}, got {t.device}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+class Context:
+    """One ss_ctx bound to a device and a stream (default: torch's current stream on that device)."""
+
+    def __init__(self, device: int | torch.device = 0, stream: torch.cuda.Stream | None = None):
+        self.lib = load_library()
+        self.device = torch.device("cuda", device if isinstance(device, int) else device.index or 0)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = self.lib.ss_create(ctypes.byref(h), self.device.index, ctypes.c_void_p(stream.cuda_stream))
+        if st != SS_OK:
+            raise SplitSolveError(st, "ss_create failed")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.ss_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def check(self, st: int):
+        if st != SS_OK:
+            msg = self.lib.ss_last_error(self.handle).decode()
+            raise SplitSolveError(st, f"{self.lib.ss_status_string(st).decode()}: {msg}")
+
+    def synchronize(self):
+        self.check(self.lib.ss_synchronize(self.handle))
+
+    def workspace_bytes(self) -> int:
+        return int(self.lib.ss_workspace_bytes(self.handle))
+
+    def kernel_timer(self, family: str | None):
+        """Start (or with None stop) bracketing launches of one kernel family with HIP events."""
+        self.check(self.lib.ss_kernel_timer(self.handle, family.encode() if family else None))
+
+    def kernel_timer_read(self):
+        """(summed milliseconds, launches) of the timed family since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_longlong()
+        self.check(self.lib.ss_kernel_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
+def ss_lead_selfenergy(ctx: Context, H00, H01, S00, S01, E, eta: float, tol: float = 0.0, max_iter: int = 0,
+                       kidx=None, sigma=None, iters=None, resid=None, info=None, validate: bool = True):
+    """Sigma_L and Sigma_R of the lead cell(s) at energies E (see ss_lead_selfenergy in splitsolve.h).
+
+    H00..S01: [nk, s, s] (or [s, s]) complex128; E: [batch] float64.  Returns (sigma [batch, 2, s, s],
+    iters [batch] int32, resid [batch, 2] float64, info [batch] int32), all on the device.
+    """
+    dev = ctx.device
+    if H00.dim() == 2:
+        H00, H01, S00, S01 = (x.unsqueeze(0) for x in (H00, H01, S00, S01))
+    nk, s, _ = H00.shape
+    for name, t in (("H00", H00), ("H01", H01), ("S00", S00), ("S01", S01)):
+        _need(t, torch.complex128, dev, name, (nk, s, s))
+    _need(E, torch.float64, dev, "E")
+    batch = E.numel()
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+        if validate:  # reads kidx back to the host (a stream synchronization)
+            _check_kidx(kidx, nk)
+    sigma = sigma if sigma is not None else torch.empty(batch, 2, s, s, dtype=torch.complex128, device=dev)
+    iters = iters if iters is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    resid = resid if resid is not None else torch.empty(batch, 2, dtype=torch.float64, device=dev)
+    info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    ctx.check(ctx.lib.ss_lead_selfenergy(
+        ctx.handle, batch, s, nk, _ptr(H00), _ptr(H01), _ptr(S00), _ptr(S01), _ptr(kidx), _ptr(E),
+        float(eta), float(tol), int(max_iter), _ptr(sigma), _ptr(iters), _ptr(resid), _ptr(info)))
+    return sigma, iters, resid, info
+
+
+def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, info=None, validate: bool = True):
+    """Q = first and last block columns of (E S - H)^{-1} for every instance (Sec. 3B, Step 1).
+
+    Hd, Sd: [nk, nb, s, s]; Hu, Su: [nk, nb-1, s, s] (or without the leading nk).  E: [batch] float64.
+    Returns (Q [batch, nb, s, 2s], info [batch] int32).
+    """
+    dev = ctx.device
+    if Hd.dim() == 3:
+        Hd, Hu, Sd, Su = (x.unsqueeze(0) for x in (Hd, Hu, Sd, Su))
+    nk, nb, s, _ = Hd.shape
+    _need(Hd, torch.complex128, dev, "Hd", (nk, nb, s, s))
+    _need(Sd, torch.complex128, dev, "Sd", (nk, nb, s, s))
+    _need(Hu, torch.complex128, dev, "Hu", (nk, nb - 1, s, s))
+    _need(Su, torch.complex128, dev, "Su", (nk, nb - 1, s, s))
+    _need(E, torch.float64, dev, "E")
+    batch = E.numel()
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+        if validate:  # reads kidx back to the host (a stream synchronization)
+            _check_kidx(kidx, nk)
+    Q = Q if Q is not None else torch.empty(batch, nb, s, 2 * s, dtype=torch.complex128, device=dev)
+    info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
+    btd = _Btd(nb, s, nk, Hd.data_ptr(), Hu.data_ptr() if nb > 1 else 0, Sd.data_ptr(),
+               Su.data_ptr() if nb > 1 else 0)
+    ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), _ptr(Q),
+                                            _ptr(info)))
+    return Q, info
+
+
+def ss_apply_obc(ctx: Context, Q, sigma, inj=None, psi=None, gc=None, info=None, want_gc: bool = True):
+    """Steps 2-4 (Sec. 3B, Eq. (x)): psi = Q (b' + z) and the corner of G^R.
+
+    Q: [batch, nb, s, 2s]; sigma: [batch, 2, s, s]; inj = b': [batch, 2s, m] or None.
+    Returns (psi [batch, nb, s, m] or None, gc [batch, 2s, 2s] or None, info [batch] int32).
+    """
+    dev = ctx.device
+    batch, nb, s, s2 = Q.shape
+    _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    m = 0
+    if inj is not None:
+        m = inj.shape[-1]
+        _need(inj, torch.complex128, dev, "inj", (batch, 2 * s, m))
+        psi = psi if psi is not None else torch.empty(batch, nb, s, m, dtype=torch.complex128, device=dev)
+        _need(psi, torch.complex128, dev, "psi", (batch, nb, s, m))
+    if want_gc:
+        gc = gc if gc is not None else torch.empty(batch, 2 * s, 2 * s, dtype=torch.complex128, device=dev)
+        _need(gc, torch.complex128, dev, "gc", (batch, 2 * s, 2 * s))
+    info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.ss_apply_obc(ctx.handle, batch, nb, s, _ptr(Q), _ptr(sigma), m, _ptr(inj), _ptr(psi),
+                                   _ptr(gc) if want_gc else None, _ptr(info)))
+    return (psi if m > 0 else None), (gc if want_gc else None), info
+
+
+def ss_transmission(ctx: Context, gc, sigma, T=None):
+    """Caroli T_LR, T_RL from the corner of G^R.  Returns T [batch, 2] float64."""
+    dev = ctx.device
+    batch, n2, _ = gc.shape
+    s = n2 // 2
+    _need(gc, torch.complex128, dev, "gc", (batch, 2 * s, 2 * s))
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    T = T if T is not None else torch.empty(batch, 2, dtype=torch.float64, device=dev)
+    _need(T, torch.float64, dev, "T", (batch, 2))
+    ctx.check(ctx.lib.ss_transmission(ctx.handle, batch, s, _ptr(gc), _ptr(sigma), _ptr(T)))
+    return T

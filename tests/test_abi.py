@@ -1,0 +1,78 @@
+"""The C-ABI library builds, loads and exports every entry point the header declares (no GPU needed).
+
+Also checks host-side argument handling of the ctypes binding.  No compute call is made here.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+import torch
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "splitsolve.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ss_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1812_01396_amd import splitsolve
+    if not os.path.exists(splitsolve.LIB_PATH):
+        from paper_1812_01396_amd import build
+        build.build(verbose=False)
+    return splitsolve.load_library()
+
+
+def test_header_declares_the_four_steps():
+    names = _declared()
+    for n in ("ss_lead_selfenergy", "ss_precompute_columns", "ss_apply_obc", "ss_transmission"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared():
+        assert hasattr(lib, name), f"{name} declared in splitsolve.h but not exported"
+
+
+def test_binding_covers_every_declared_symbol():
+    from paper_1812_01396_amd import splitsolve
+    assert sorted(splitsolve.EXPORTS) == _declared()
+
+
+def test_status_strings(lib):
+    for code in range(5):
+        assert lib.ss_status_string(code)
+    assert lib.ss_status_string(99) == b"unknown status"
+
+
+def test_null_arguments_are_rejected_without_a_device(lib):
+    # a null context and a null output pointer are host-detectable: no device work is attempted
+    assert lib.ss_create(None, 0, None) == 1
+    assert lib.ss_transmission(None, 1, 4, None, None, None) == 1
+    assert lib.ss_synchronize(None) == 1
+    assert lib.ss_workspace_bytes(None) == 0
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")
+def test_create_fails_cleanly_without_gpu(lib):
+    h = ctypes.c_void_p()
+    assert lib.ss_create(ctypes.byref(h), 0, None) != 0
+    assert not h.value
+
+
+def test_binding_validates_tensors():
+    from paper_1812_01396_amd import splitsolve
+    dev = torch.device("cuda", 0)
+    x = torch.zeros(2, 2, dtype=torch.complex64)
+    with pytest.raises(TypeError):
+        splitsolve._need(x, torch.complex128, dev, "x")
+    y = torch.zeros(2, 2, dtype=torch.complex128)
+    with pytest.raises(ValueError):
+        splitsolve._need(y, torch.complex128, dev, "y")  # wrong device
+    with pytest.raises(ValueError):
+        splitsolve._check_kidx(torch.tensor([0, 3], dtype=torch.int32), 2)

@@ -1,0 +1,148 @@
+"""Parity of the HIP path (through the C ABI) against the CPU oracle, element by element.
+
+Tolerances (FP64 path): relative Frobenius error <= 1e-10 for Q, Sigma, the corner of G^R and psi;
+|T - T_ref| / max(1, T_ref) <= 1e-10.  Inputs are seeded synthetic instances from ``synth``; sizes
+span several 64-wide tiles, a ragged tail and the degenerate nb = 1 case.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import linalg, selfenergy, transport
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1812_01396_amd as ss
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = ss.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _stack_sets(insts):
+    return [np.stack([getattr(i, f) for i in insts]) for f in ("Hd", "Hu", "Sd", "Su")]
+
+
+@pytest.mark.parametrize("nb,s", [(1, 5), (2, 16), (5, 40), (3, 72), (4, 130), (2, 33)])
+def test_precompute_columns_vs_oracle(ctx, nb, s):
+    import paper_1812_01396_amd as ss
+    print(f"precompute nb={nb} s={s}", flush=True)
+    insts = [synth.random_btd(nb, s, seed=1000 + 7 * nb + s + k) for k in range(2)]
+    Es = np.array([0.31, -0.47, 0.05])
+    kidx = np.array([0, 1, 1], dtype=np.int32)
+    hd, hu, sd, su = _stack_sets(insts)
+    q, info = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), _dev(Es, torch.float64),
+                                       kidx=_dev(kidx, torch.int32))
+    torch.cuda.synchronize()
+    q = q.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    for b, (E, k) in enumerate(zip(Es, kidx)):
+        ad, au, al = transport.device_blocks(insts[k].Hd, insts[k].Hu, insts[k].Sd, insts[k].Su, E)
+        ref = transport.first_last_columns(ad, au, al)
+        assert _rel(q[b], ref) <= TOL, (b, _rel(q[b], ref))
+
+
+def test_precompute_columns_zero_pivot_code(ctx):
+    """A decoupled device with E on an onsite level: exactly zero pivots, reported LAPACK-style."""
+    import paper_1812_01396_amd as ss
+    nb, s = 3, 4
+    hd = np.repeat(np.diag([1.0, 2.0, 3.0, 4.0]).astype(np.complex128)[None], nb, 0)
+    hu = np.zeros((nb - 1, s, s), np.complex128)
+    sd = np.repeat(np.eye(s, dtype=np.complex128)[None], nb, 0)
+    su = np.zeros_like(hu)
+    E = np.array([2.0, 2.5])
+    _, info = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), _dev(E, torch.float64))
+    torch.cuda.synchronize()
+    # E = 2: block 1 (first system of the last-column recursion) is diag(1, 0, -1, -2) -> column 2 of block 1
+    assert info.cpu().tolist() == [2, 0]
+
+
+@pytest.mark.parametrize("cell_kind,s", [("chain", 16), ("dft", 24), ("dft", 40), ("chain", 70)])
+def test_selfenergy_vs_oracle(ctx, cell_kind, s):
+    import paper_1812_01396_amd as ss
+    print(f"selfenergy {cell_kind} s={s}", flush=True)
+    cells = [synth.chain_cell(s, 5), synth.chain_cell(s, 6)] if cell_kind == "chain" else \
+        [synth.dft_like_cell(s, 3, 0.4), synth.dft_like_cell(s, 3, 1.7)]
+    Es = np.array([-1.3, 0.2, 0.9, 2.7]) if cell_kind == "chain" else np.array([-3.0, -0.5, 1.1, 4.2])
+    kidx = np.array([0, 1, 0, 1], dtype=np.int32)
+    eta = 1e-8
+    h00, h01, s00, s01 = (np.stack([c[i] for c in cells]) for i in range(4))
+    sig, iters, resid, info = ss.ss_lead_selfenergy(ctx, _dev(h00), _dev(h01), _dev(s00), _dev(s01),
+                                                    _dev(Es, torch.float64), eta, kidx=_dev(kidx, torch.int32))
+    torch.cuda.synchronize()
+    sig = sig.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all(), info
+    assert (resid.cpu().numpy() <= 1e-10).all(), resid
+    for b, (E, k) in enumerate(zip(Es, kidx)):
+        a0, a1, am1 = selfenergy.lead_blocks(*cells[k], E, eta)
+        sl, sr, it, conv = selfenergy.decimation(a0, a1, am1)
+        assert abs(int(iters[b]) - it) <= 1
+        assert _rel(sig[b, 0], sl) <= TOL, (b, _rel(sig[b, 0], sl))
+        assert _rel(sig[b, 1], sr) <= TOL, (b, _rel(sig[b, 1], sr))
+
+
+def _pipeline(ctx, inst_sets, Es, kidx, eta, inj):
+    import paper_1812_01396_amd as ss
+    hd, hu, sd, su = _stack_sets(inst_sets)
+    leads = [np.stack([getattr(i, f) for i in inst_sets]) for f in ("H00", "H01", "S00", "S01")]
+    E_d, k_d = _dev(Es, torch.float64), _dev(kidx, torch.int32)
+    sig, iters, resid, info_s = ss.ss_lead_selfenergy(ctx, *(_dev(x) for x in leads), E_d, eta, kidx=k_d)
+    q, info_q = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), E_d, kidx=k_d)
+    psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=_dev(inj) if inj is not None else None)
+    T = ss.ss_transmission(ctx, gc, sig)
+    torch.cuda.synchronize()
+    for i in (info_s, info_q, info_o):
+        assert (i.cpu().numpy() == 0).all(), i
+    return dict(sigma=sig.cpu().numpy(), q=q.cpu().numpy(), psi=None if psi is None else psi.cpu().numpy(),
+                gc=gc.cpu().numpy(), T=T.cpu().numpy())
+
+
+@pytest.mark.parametrize("nb,s,m", [(1, 6, 2), (4, 40, 3), (3, 72, 5), (2, 100, 1)])
+def test_obc_psi_transmission_vs_oracle(ctx, nb, s, m):
+    print(f"pipeline nb={nb} s={s} m={m}", flush=True)
+    insts = [synth.random_btd(nb, s, seed=2000 + s + k) for k in range(2)]
+    Es = np.array([0.15, -0.35])
+    kidx = np.array([0, 1], dtype=np.int32)
+    eta = 1e-8
+    inj = np.stack([synth.injection_block(s, m, 50 + b) for b in range(2)])
+    out = _pipeline(ctx, insts, Es, kidx, eta, inj)
+    for b in range(2):
+        inst = insts[kidx[b]]
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
+                                       inst.S01, Es[b], eta, inj=inj[b])
+        assert _rel(out["gc"][b], ref["gc"]) <= TOL
+        assert _rel(out["psi"][b], ref["psi"]) <= TOL
+        for j, key in enumerate(("t_lr", "t_rl")):
+            assert abs(out["T"][b, j] - ref[key]) <= TOL * max(1.0, abs(ref[key]))
+
+
+def test_chain_crystal_all_energies(ctx):
+    """Random 16-orbital chain, 32 blocks, 64 energies in [-3, 3]: T equals the stored channel counts."""
+    import os
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "chain16_channels.txt"), comments="#")
+    cell = synth.chain_cell(16, 0)
+    inst = synth.device_from_cell(cell, 32)
+    Es = rows[:, 0]
+    out = _pipeline(ctx, [inst], Es, np.zeros(len(Es), np.int32), 1e-8, None)
+    for b, E in enumerate(Es):
+        assert abs(out["T"][b, 0] - rows[b, 1]) <= 1e-8, (E, out["T"][b], rows[b, 1])
+        assert abs(out["T"][b, 1] - rows[b, 1]) <= 1e-8
+    # and element-wise against the oracle on a sample of energies
+    for b in range(0, len(Es), 9):
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, *cell, Es[b], 1e-8)
+        assert _rel(out["q"][b], ref["q"]) <= TOL
+        assert abs(out["T"][b, 0] - ref["t_lr"]) <= TOL * max(1.0, ref["t_lr"])
