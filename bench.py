@@ -101,6 +101,90 @@ def cpu_baseline(w, insts, E, kidx, inj, sample: int, T_gpu):
                        f"{dt:.1f} s wall"), float(max(errs))
 
 
+class Pipeline:
+    """The whole hot path for every instance of a workload, inputs resident on the GPU.
+
+    run() enqueues one step: self-energies on a second stream (overlapping the first chunk's
+    recursion), then per chunk of instances Q, the open-boundary correction with psi and the corner
+    of G^R, and T.  Outputs stay on the device (sigma, iters, resid, psi, gc, T, info_*).
+    """
+
+    def __init__(self, workload: str, chunk: int = 0):
+        import torch
+
+        import paper_1812_01396_amd as ss
+
+        self.ss, self.torch = ss, torch
+        w, insts, E_np, kidx_np, inj_np = build_inputs(workload)
+        self.w, self.insts, self.E_np, self.kidx_np, self.inj_np = w, insts, E_np, kidx_np, inj_np
+        s, nb, m = w["s"], w["nb"], w["m"]
+        self.chunk = chunk or w["chunk"]
+        self.n = nb_inst = len(E_np)
+        dev = self.dev = torch.device("cuda", 0)
+
+        def t(a, dt=torch.complex128):
+            return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+
+        self.Hd = t(np.stack([i.Hd for i in insts]))
+        self.Hu = t(np.stack([i.Hu for i in insts]))
+        self.Sd = t(np.stack([i.Sd for i in insts]))
+        self.Su = t(np.stack([i.Su for i in insts]))
+        self.lead = [t(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01")]
+        self.E = t(E_np, torch.float64)
+        self.kidx = t(kidx_np, torch.int32)
+        self.inj = t(inj_np)
+        c128 = torch.complex128
+        self.sigma = torch.empty(nb_inst, 2, s, s, dtype=c128, device=dev)
+        self.iters = torch.empty(nb_inst, dtype=torch.int32, device=dev)
+        self.resid = torch.empty(nb_inst, 2, dtype=torch.float64, device=dev)
+        self.info_s = torch.empty(nb_inst, dtype=torch.int32, device=dev)
+        self.Qbuf = torch.empty(self.chunk, nb, s, 2 * s, dtype=c128, device=dev)
+        self.psi = torch.empty(nb_inst, nb, s, m, dtype=c128, device=dev)
+        self.gc = torch.empty(nb_inst, 2 * s, 2 * s, dtype=c128, device=dev)
+        self.T = torch.empty(nb_inst, 2, dtype=torch.float64, device=dev)
+        self.info_q = torch.empty(nb_inst, dtype=torch.int32, device=dev)
+        self.info_o = torch.empty(nb_inst, dtype=torch.int32, device=dev)
+        self.stream_main = torch.cuda.current_stream(dev)
+        self.stream_sig = torch.cuda.Stream(dev)  # default priority
+        self.ctx = ss.Context(0, self.stream_main)
+        self.ctx_s = ss.Context(0, self.stream_sig)
+        ss.splitsolve._check_kidx(self.kidx, len(insts))  # once: the step itself never reads back to the host
+
+    def run(self):
+        ss, torch, w = self.ss, self.torch, self.w
+        # the previous step's readers of sigma (main stream) finish before sigma is overwritten
+        prev = torch.cuda.Event()
+        prev.record(self.stream_main)
+        done = torch.cuda.Event()
+        err = []
+
+        def run_sigma():
+            try:
+                with torch.cuda.stream(self.stream_sig):
+                    self.stream_sig.wait_event(prev)
+                    ss.ss_lead_selfenergy(self.ctx_s, *self.lead, self.E, w["eta"], kidx=self.kidx, sigma=self.sigma,
+                                          iters=self.iters, resid=self.resid, info=self.info_s, validate=False)
+                    done.record(self.stream_sig)
+            except Exception as e:  # surfaced after join
+                err.append(e)
+
+        th = threading.Thread(target=run_sigma)
+        th.start()
+        for c0 in range(0, self.n, self.chunk):
+            c1 = min(c0 + self.chunk, self.n)
+            q = self.Qbuf[: c1 - c0]
+            ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
+                                     kidx=self.kidx[c0:c1], Q=q, info=self.info_q[c0:c1], validate=False)
+            if c0 == 0:
+                th.join()
+                if err:
+                    raise err[0]
+                self.stream_main.wait_event(done)
+            ss.ss_apply_obc(self.ctx, q, self.sigma[c0:c1], inj=self.inj[c0:c1], psi=self.psi[c0:c1],
+                            gc=self.gc[c0:c1], info=self.info_o[c0:c1])
+            ss.ss_transmission(self.ctx, self.gc[c0:c1], self.sigma[c0:c1], T=self.T[c0:c1])
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,103 +205,31 @@ def main():
 
     import torch
 
-    import paper_1812_01396_amd as ss
-
-    w, insts, E_np, kidx_np, inj_np = build_inputs(args.workload)
-    s, nb, m = w["s"], w["nb"], w["m"]
-    chunk = args.chunk or w["chunk"]
-    nbatch = len(E_np)
-    dev = torch.device("cuda", 0)
-
-    def t(a, dt=torch.complex128):
-        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
-
-    Hd = t(np.stack([i.Hd for i in insts]))
-    Hu = t(np.stack([i.Hu for i in insts]))
-    Sd = t(np.stack([i.Sd for i in insts]))
-    Su = t(np.stack([i.Su for i in insts]))
-    H00, H01, S00, S01 = (t(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01"))
-    E = t(E_np, torch.float64)
-    kidx = t(kidx_np, torch.int32)
-    inj = t(inj_np)
-    sigma = torch.empty(nbatch, 2, s, s, dtype=torch.complex128, device=dev)
-    iters = torch.empty(nbatch, dtype=torch.int32, device=dev)
-    resid = torch.empty(nbatch, 2, dtype=torch.float64, device=dev)
-    info_s = torch.empty(nbatch, dtype=torch.int32, device=dev)
-    Qbuf = torch.empty(chunk, nb, s, 2 * s, dtype=torch.complex128, device=dev)
-    psi = torch.empty(nbatch, nb, s, m, dtype=torch.complex128, device=dev)
-    gc = torch.empty(nbatch, 2 * s, 2 * s, dtype=torch.complex128, device=dev)
-    T = torch.empty(nbatch, 2, dtype=torch.float64, device=dev)
-    info_q = torch.empty(nbatch, dtype=torch.int32, device=dev)
-    info_o = torch.empty(nbatch, dtype=torch.int32, device=dev)
-
-    stream_main = torch.cuda.current_stream(dev)
-    stream_obc = torch.cuda.Stream(dev)
-    ctx = ss.Context(0, stream_main)
-    ctx_s = ss.Context(0, stream_obc)
+    pipe = Pipeline(args.workload, args.chunk)
+    w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel
-    sig_ctx_families = {"dec_update"}
-
-    ss.splitsolve._check_kidx(kidx, len(insts))  # validated once here; the hot loop skips the host sync
-
-    def step():
-        # self-energies on their own stream, overlapping the first chunks' recursions; the previous
-        # step's readers of sigma on the main stream must finish before it is overwritten
-        prev = torch.cuda.Event()
-        prev.record(stream_main)
-        done = torch.cuda.Event()
-        err = []
-
-        def run_sigma():
-            try:
-                with torch.cuda.stream(stream_obc):
-                    stream_obc.wait_event(prev)
-                    ss.ss_lead_selfenergy(ctx_s, H00, H01, S00, S01, E, w["eta"], kidx=kidx, sigma=sigma,
-                                          iters=iters, resid=resid, info=info_s, validate=False)
-                    done.record(stream_obc)
-            except Exception as e:  # surfaced after join
-                err.append(e)
-
-        th = threading.Thread(target=run_sigma)
-        th.start()
-        for c0 in range(0, nbatch, chunk):
-            c1 = min(c0 + chunk, nbatch)
-            q = Qbuf[: c1 - c0]
-            ss.ss_precompute_columns(ctx, Hd, Hu, Sd, Su, E[c0:c1], kidx=kidx[c0:c1], Q=q, info=info_q[c0:c1],
-                                     validate=False)
-            if c0 == 0:
-                th.join()
-                if err:
-                    raise err[0]
-                stream_main.wait_event(done)
-            ss.ss_apply_obc(ctx, q, sigma[c0:c1], inj=inj[c0:c1], psi=psi[c0:c1], gc=gc[c0:c1],
-                            info=info_o[c0:c1])
-            ss.ss_transmission(ctx, gc[c0:c1], sigma[c0:c1], T=T[c0:c1])
+    timed_ctx = pipe.ctx_s if fam in ("dec_update",) else pipe.ctx
 
     for _ in range(args.warmup):
-        step()
+        pipe.run()
     torch.cuda.synchronize()
-    timed_ctx = ctx_s if fam in sig_ctx_families else ctx
     timed_ctx.kernel_timer(fam)
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        pipe.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     k_ms, k_launches = timed_ctx.kernel_timer_read()
     timed_ctx.kernel_timer(None)
 
-    it_np = iters.cpu().numpy().astype(np.float64)
-    T_np = T.cpu().numpy()
-    bad = int((info_s.cpu() != 0).sum() + (info_q.cpu() != 0).sum() + (info_o.cpu() != 0).sum())
+    it_np = pipe.iters.cpu().numpy().astype(np.float64)
+    T_np = pipe.T.cpu().numpy()
+    bad = int((pipe.info_s.cpu() != 0).sum() + (pipe.info_q.cpu() != 0).sum() + (pipe.info_o.cpu() != 0).sum())
     ms_per_step = elapsed * 1e3 / args.steps
     value = nbatch * args.steps / elapsed
 
     # algorithmic flops of one step
-    f_sweep = nbatch * sweep_flops(nb, s)
-    f_dec = dec_flops(s, float(it_np.sum()))
-    f_obc = nbatch * obc_flops(nb, s, m)
-    f_step = f_sweep + f_dec + f_obc
+    f_step = nbatch * sweep_flops(nb, s) + dec_flops(s, float(it_np.sum())) + nbatch * obc_flops(nb, s, m)
     fam_flops = {
         "dec_update": args.steps * 32.0 * s**3 * float(it_np.sum()),
         "form": args.steps * nbatch * 2 * (nb - 1) * 8.0 * s**3,
@@ -233,7 +245,7 @@ def main():
     cpu = None
     t_err = None
     if not args.no_cpu_baseline and args.cpu_sample > 0:
-        cpu, t_err = cpu_baseline(w, insts, E_np, kidx_np, inj_np, args.cpu_sample, T_np)
+        cpu, t_err = cpu_baseline(w, pipe.insts, pipe.E_np, pipe.kidx_np, pipe.inj_np, args.cpu_sample, T_np)
 
     out = {
         "metric": "(E,k) solves/sec",
@@ -249,7 +261,7 @@ def main():
         "dtype": "c128",
         "data": "synthetic",
         "config": {"workload": args.workload, "s": s, "nb": nb, "instances": nbatch, "energies": w["n_e"],
-                   "k_points": len(w["ks"]), "m_inj": m, "eta": w["eta"], "chunk": chunk,
+                   "k_points": len(w["ks"]), "m_inj": m, "eta": w["eta"], "chunk": pipe.chunk,
                    "precision": "fp64"},
         "tflops_step": round(f_step / (ms_per_step * 1e-3) / 1e12, 3),
         "frac_fp64_peak_step": round(f_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),

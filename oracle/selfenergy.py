@@ -69,6 +69,33 @@ def decimation(a0, a1, am1, tol: float = 1e-14, max_iter: int = 200):
     return sigma_l, sigma_r, it, converged
 
 
+def decimation_conditioning(a0, a1, am1, tol: float = 1e-14, max_iter: int = 200) -> float:
+    """Largest 1-norm condition estimate of eps over the passes of ``decimation`` (same recursion).
+
+    Every pass solves with eps; a solve carries a forward error of order u * cond(eps), so this bounds
+    how far two correct finite-precision runs of the decimation may drift apart.  Used only to set
+    comparison tolerances.
+    """
+    import scipy.linalg as sla
+
+    eps = a0.copy()
+    alpha = a1.copy()
+    beta = am1.copy()
+    scale = _maxabs(a0)
+    worst = 1.0
+    for _ in range(max_iter):
+        lu, piv = sla.lu_factor(eps)
+        rcond, _info = sla.lapack.zgecon(lu, np.linalg.norm(eps, 1), norm="1")
+        worst = max(worst, 1.0 / max(float(rcond), 1e-300))
+        g_beta = sla.lu_solve((lu, piv), beta)
+        g_alpha = sla.lu_solve((lu, piv), alpha)
+        eps = eps - alpha @ g_beta - beta @ g_alpha
+        alpha, beta = -(alpha @ g_alpha), -(beta @ g_beta)
+        if _maxabs(alpha) + _maxabs(beta) <= tol * scale:
+            break
+    return worst
+
+
 def quadratic_residuals(a0, a1, am1, sigma_l, sigma_r):
     """Relative Frobenius residuals of the fixed-point equations of Sigma_R and Sigma_L.
 

@@ -45,6 +45,15 @@ def first_last_columns(ad, au, al):
     return btd_solve(ad, au, al, boundary_rhs(nb, s, top, bottom))
 
 
+def first_last_columns_mirrored(ad, au, al):
+    """Q by the same definition but eliminated in the opposite block order (block Thomas on the
+    reversed matrix).  Both results are exact up to rounding; their difference measures how strongly
+    this instance amplifies rounding (used only to set comparison tolerances)."""
+    s = ad.shape[1]
+    qr = first_last_columns(ad[::-1].copy(), al[::-1].copy(), au[::-1].copy())
+    return np.concatenate([qr[::-1][:, :, s:], qr[::-1][:, :, :s]], axis=2)
+
+
 def open_diag(ad, sigma_l, sigma_r):
     """Diagonal blocks of T = A - Sigma: Sigma_L enters block 1, Sigma_R block n_B."""
     td = ad.copy()

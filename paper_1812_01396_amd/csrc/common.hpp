@@ -54,7 +54,6 @@ struct Buffer {
 enum Slot {
   kSlotM = 0,      // augmented matrices of the batched LU solves
   kSlotPerm,       // row permutations
-  kSlotTri,        // inverted diagonal blocks of L and U
   kSlotZp,         // first zero pivot per factorization
   kSlotX,          // per-step solutions of the recursion
   kSlotInst,       // per-matrix instance tables

@@ -1,32 +1,26 @@
 // Batched dense complex LU with partial pivoting and the two triangular solves, on gfx950.
 //
-// Left-looking (Crout) blocked factorization of the augmented matrix [D | RHS], panel width W:
-//   for each panel p (columns [r0, r0+w)):
-//     1. panel update   A[r0:, panel] -= L[r0:, :r0] U[:r0, panel]                (MFMA tiles)
-//     2. panel factor   pivot search (|Re|+|Im|, lowest row on ties, as LAPACK), row
-//                       interchange in the logical row map, scaling and rank-1 updates, all in
-//                       registers of one workgroup per system; inverts the W x W diagonal blocks
-//                       of L and U for the later tile solves
-//     3. row block      U[panel rows, r0+w:] = L11^{-1} (A[panel rows, r0+w:] - L[rows, :r0] U[:r0, r0+w:])
-//                       over the remaining D columns and all RHS columns (MFMA tiles, then the
-//                       inverted L11 applied inside the tile)
-//   back substitution, block rows from the bottom:
-//     X[rows] = U11^{-1} (Y[rows] - U[rows, r0+w:n] X[r0+w:n])                    (MFMA tiles)
-// Rows are never moved in memory; `perm` maps logical rows to physical rows.
+// Each system is an augmented row-major matrix [D | RHS] (n rows).  Rows are never moved in memory:
+// a logical-to-physical row map `perm` records the interchanges and every kernel addresses rows
+// through it (row segments stay contiguous, so loads stay coalesced).
+//
+// Recursive (column-halving) factorization, so that almost all flops are large MFMA products:
+//   lu(c0, c1):  if c1 - c0 <= W: factor the panel in registers (pivot search |Re|+|Im| with the
+//                lowest row on ties as in LAPACK, interchange in the row map, scale, rank-1 updates)
+//                else with cm the midpoint (a multiple of W):
+//                  lu(c0, cm);  L11^{-1} on rows [c0, cm) of columns [cm, c1);
+//                  A[cm:n, cm:c1] -= L[cm:n, c0:cm] U[c0:cm, cm:c1];  lu(cm, c1)
+// then the right-hand sides: Y = L^{-1} P RHS and X = U^{-1} Y by recursive triangular solves whose
+// leaves are W-row substitutions inside a tile and whose inner nodes are MFMA products.
 #include "lu.hpp"
 #include "tile.hpp"
 
+#include <algorithm>
 #include <climits>
-#include <utility>
 
 namespace ss {
 
 int lu_panel_width(int n) { return n <= 512 ? 32 : (n <= 1024 ? 16 : 8); }
-
-long lu_tri_elems(int n) {
-  const int w = lu_panel_width(n);
-  return (long)cdiv(n, w) * 2 * w * w;
-}
 
 struct LuArgs {
   double2 *M;
@@ -34,8 +28,6 @@ struct LuArgs {
   int ldm;
   int *perm;
   long sP;
-  double2 *tri;
-  long sT;
   int *zp;
   double2 *X;
   long sX;
@@ -51,7 +43,7 @@ __device__ __forceinline__ bool skipped(const LuArgs &a, int mat) {
 
 static LuArgs make_args(const LuDesc &d) {
   LuArgs a;
-  a.M = d.M; a.sM = d.sM; a.ldm = d.ldm; a.perm = d.perm; a.sP = d.sP; a.tri = d.tri; a.sT = d.sT;
+  a.M = d.M; a.sM = d.sM; a.ldm = d.ldm; a.perm = d.perm; a.sP = d.sP;
   a.zp = d.zp; a.X = d.X; a.sX = d.sX; a.ldx = d.ldx; a.n = d.n; a.nrhs = d.nrhs;
   a.skip = d.skip; a.skip_shift = d.skip_shift;
   return a;
@@ -64,121 +56,30 @@ __global__ void k_identity_perm(int *perm, long sP, int n) {
 
 // ------------------------------------------------------------------ panel factorization
 
-struct PanelShared {
-  double red_v[16];
-  int red_i[16];
-};
-
-// One column step of the panel factorization for compile-time column J (keeps v in registers).
-template <int J, int W, int R>
-__device__ __forceinline__ void panel_column(double2 (&v)[R * W], double2 (*rowbuf)[W], int *sperm, PanelShared &ps,
-                                             int T, int nrows, int w, int r0, int &zero_col) {
-  if (J >= w) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, nw = T >> 6;
-  // ---- pivot search: largest |Re|+|Im| in column J among logical rows >= J, lowest row on ties
-  double bv = -1.0;
-  int bi = INT_MAX;
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * T;
-    if (lr >= J && lr < nrows) {
-      const double t = cabs1(v[q * W + J]);
-      if (t > bv) { bv = t; bi = lr; }
-    }
-  }
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double ov = __shfl_xor(bv, off);
-    const int oi = __shfl_xor(bi, off);
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-  }
-  if (lane == 0) { ps.red_v[wave] = bv; ps.red_i[wave] = bi; }
-  __syncthreads();
-  bv = ps.red_v[0];
-  bi = ps.red_i[0];
-  for (int ww = 1; ww < nw; ++ww) {
-    const double ov = ps.red_v[ww];
-    const int oi = ps.red_i[ww];
-    if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-  }
-  // no finite candidate (NaN column): keep the diagonal row so indexing stays in range
-  const int piv = (bi >= J && bi < nrows) ? bi : J;
-  // ---- interchange logical rows J and piv (data travels between the two owning threads)
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * T;
-    if (lr == piv) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) st2(rowbuf[0][c], v[q * W + c]);
-    }
-    if (lr == J && piv != J) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) st2(rowbuf[1][c], v[q * W + c]);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < R; ++q) {
-    const int lr = tid + q * T;
-    if (lr == J) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) v[q * W + c] = ld2(rowbuf[0][c]);
-    } else if (lr == piv) {
-#pragma unroll
-      for (int c = 0; c < W; ++c) v[q * W + c] = ld2(rowbuf[1][c]);
-    }
-  }
-  if (tid == 0 && piv != J) {
-    const int t = sperm[J];
-    sperm[J] = sperm[piv];
-    sperm[piv] = t;
-  }
-  // ---- eliminate below the pivot
-  const double2 u = ld2(rowbuf[0][J]);
-  if (u.x == 0.0 && u.y == 0.0) {
-    if (zero_col == 0) zero_col = r0 + J + 1;
-  } else {
-    const double2 ui = crecip(u);
-#pragma unroll
-    for (int q = 0; q < R; ++q) {
-      const int lr = tid + q * T;
-      if (lr > J && lr < nrows) {
-        const double2 l = cmul(v[q * W + J], ui);
-        v[q * W + J] = l;
-#pragma unroll
-        for (int c = J + 1; c < W; ++c) v[q * W + c] = cfnms(v[q * W + c], l, ld2(rowbuf[0][c]));
-      }
-    }
-  }
-}
-
-template <int W, int R, int... J>
-__device__ __forceinline__ void panel_columns(std::integer_sequence<int, J...>, double2 (&v)[R * W],
-                                              double2 (*rowbuf)[W], int *sperm, PanelShared &ps, int T, int nrows,
-                                              int w, int r0, int &zero_col) {
-  (panel_column<J, W, R>(v, rowbuf, sperm, ps, T, nrows, w, r0, zero_col), ...);
-}
-
+// One workgroup per system factors logical rows [c0, n) of columns [c0, c0+w).  Each thread keeps R
+// rows of the panel in registers.  The column loop runs at run time (a fully unrolled loop would not
+// fit the instruction cache) and the registers are only ever addressed with compile-time indices:
+// after each column every row is rotated left by one position, so the current column always sits in
+// position 0 and the finished entry moves to position W-1; after W rotations the order is restored.
 template <int W, int R, int LB>
-__global__ void __launch_bounds__(LB) k_panel(LuArgs a, int r0, int p) {
+__global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   const int mat = blockIdx.x;
   if (skipped(a, mat)) return;
-  const int tid = threadIdx.x, T = blockDim.x;
+  const int tid = threadIdx.x, T = blockDim.x, lane = tid & 63, wave = tid >> 6, nw = T >> 6;
   double2 *M = a.M + (long)mat * a.sM;
   int *perm = a.perm + (long)mat * a.sP;
-  const int nrows = a.n - r0;
+  const int nrows = a.n - c0;
   const int w = min(W, nrows);
   const long ld = a.ldm;
 
   __shared__ int sperm[LB * R];
-  __shared__ PanelShared ps;
+  __shared__ double red_v[16];
+  __shared__ int red_i[16];
   __shared__ double2 rowbuf[2][W];
-  __shared__ double2 blk[W][W + 1];
-  __shared__ double2 inv[W][W + 1];
 
   for (int q = 0; q < R; ++q) {
     const int lr = tid + q * T;
-    if (lr < nrows) sperm[lr] = perm[r0 + lr];
+    if (lr < nrows) sperm[lr] = perm[c0 + lr];
   }
   __syncthreads();
 
@@ -188,11 +89,110 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int r0, int p) {
     const int lr = tid + q * T;
 #pragma unroll
     for (int c = 0; c < W; ++c)
-      v[q * W + c] = (lr < nrows && c < w) ? M[(long)sperm[lr] * ld + r0 + c] : make_double2(0.0, 0.0);
+      v[q * W + c] = (lr < nrows && c < w) ? M[(long)sperm[lr] * ld + c0 + c] : make_double2(0.0, 0.0);
   }
 
   int zero_col = 0;
-  panel_columns<W, R>(std::make_integer_sequence<int, W>{}, v, rowbuf, sperm, ps, T, nrows, w, r0, zero_col);
+#pragma unroll 1
+  for (int j = 0; j < w; ++j) {
+    // ---- pivot search in column j (register position 0) over logical rows >= j
+    double bv = -1.0;
+    int bi = INT_MAX;
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int lr = tid + q * T;
+      if (lr >= j && lr < nrows) {
+        const double t = cabs1(v[q * W]);
+        if (t > bv) { bv = t; bi = lr; }
+      }
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int oi = __shfl_xor(bi, off);
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+    __syncthreads();
+    bv = red_v[0];
+    bi = red_i[0];
+    for (int ww = 1; ww < nw; ++ww) {
+      const double ov = red_v[ww];
+      const int oi = red_i[ww];
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    }
+    // no finite candidate (NaN column): keep the diagonal row so indexing stays in range
+    const int piv = (bi >= j && bi < nrows) ? bi : j;
+    // ---- interchange logical rows j and piv (data travels between the two owning threads)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int lr = tid + q * T;
+      if (lr == piv) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) st2(rowbuf[0][c], v[q * W + c]);
+      }
+      if (lr == j && piv != j) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) st2(rowbuf[1][c], v[q * W + c]);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int lr = tid + q * T;
+      if (lr == j) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[q * W + c] = ld2(rowbuf[0][c]);
+      } else if (lr == piv) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) v[q * W + c] = ld2(rowbuf[1][c]);
+      }
+    }
+    if (tid == 0 && piv != j) {
+      const int t = sperm[j];
+      sperm[j] = sperm[piv];
+      sperm[piv] = t;
+    }
+    // ---- eliminate below the pivot and rotate: l = a_rj / u_jj, a_rc -= l u_jc for columns c > j
+    const double2 u = ld2(rowbuf[0][0]);
+    const bool live = !(u.x == 0.0 && u.y == 0.0);
+    if (!live && zero_col == 0) zero_col = c0 + j + 1;
+    const double2 ui = live ? crecip(u) : make_double2(0.0, 0.0);
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int lr = tid + q * T;
+      const bool below = live && lr > j && lr < nrows;
+      const double2 v0 = v[q * W];
+      const double2 p = cmul(v0, ui);
+      const double lx = below ? p.x : v0.x, ly = below ? p.y : v0.y;
+#pragma unroll
+      for (int c = 0; c < W - 1; ++c) {
+        // position c + 1 holds column j + 1 + c while c < W - 1 - j (later columns); the rest are done
+        const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
+        const double vx = v[q * W + c + 1].x, vy = v[q * W + c + 1].y;
+        const bool upd = below && (c < W - 1 - j);
+        v[q * W + c].x = upd ? vx - lx * ux + ly * uy : vx;
+        v[q * W + c].y = upd ? vy - lx * uy - ly * ux : vy;
+      }
+      v[q * W + W - 1].x = lx;
+      v[q * W + W - 1].y = ly;
+    }
+  }
+  // complete the rotation for a narrow last panel (w < W) so position c holds column c again
+#pragma unroll 1
+  for (int t = w; t < W; ++t) {
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const double x0 = v[q * W].x, y0 = v[q * W].y;
+#pragma unroll
+      for (int c = 0; c < W - 1; ++c) {
+        v[q * W + c].x = v[q * W + c + 1].x;
+        v[q * W + c].y = v[q * W + c + 1].y;
+      }
+      v[q * W + W - 1].x = x0;
+      v[q * W + W - 1].y = y0;
+    }
+  }
   __syncthreads();  // sperm final
 
   // ---- write the factored panel back (rows stay in their physical place) and the row map
@@ -202,221 +202,221 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int r0, int p) {
     if (lr < nrows) {
 #pragma unroll
       for (int c = 0; c < W; ++c)
-        if (c < w) M[(long)sperm[lr] * ld + r0 + c] = v[q * W + c];
-      perm[r0 + lr] = sperm[lr];
+        if (c < w) M[(long)sperm[lr] * ld + c0 + c] = v[q * W + c];
+      perm[c0 + lr] = sperm[lr];
     }
   }
   if (tid == 0) {
-    if (p == 0) a.zp[mat] = zero_col;
+    if (c0 == 0) a.zp[mat] = zero_col;
     else if (zero_col != 0 && a.zp[mat] == 0) a.zp[mat] = zero_col;
   }
-
-  // ---- invert the diagonal blocks: L11 (unit lower) and U11 (upper), padded with the identity
-  if (tid < W) {
-#pragma unroll
-    for (int c = 0; c < W; ++c) {
-      double2 e = make_double2(tid == c ? 1.0 : 0.0, 0.0);
-      st2(blk[tid][c], (tid < w && c < w) ? v[c] : e);
-    }
-  }
-  __syncthreads();
-  if (tid < W) {
-    const int c = tid;
-    // column c of L11^{-1}
-    for (int i = 0; i < W; ++i) {
-      double2 x;
-      if (i < c) x = make_double2(0.0, 0.0);
-      else if (i == c) x = make_double2(1.0, 0.0);
-      else {
-        x = make_double2(0.0, 0.0);
-        for (int k = c; k < i; ++k) x = cfnms(x, ld2(blk[i][k]), ld2(inv[k][c]));
-      }
-      st2(inv[i][c], x);
-    }
-  }
-  __syncthreads();
-  double2 *tL = a.tri + (long)mat * a.sT + (long)p * 2 * W * W;
-  double2 *tU = tL + W * W;
-  for (int idx = tid; idx < W * W; idx += T) tL[idx] = ld2(inv[idx / W][idx % W]);
-  __syncthreads();
-  if (tid < W) {
-    const int c = tid;
-    // column c of U11^{-1}: x_c = 1/U_cc, x_i = -(sum_{k=i+1..c} U_ik x_k) / U_ii
-    for (int i = W - 1; i >= 0; --i) {
-      double2 x = make_double2(0.0, 0.0);
-      if (i == c) x = crecip(ld2(blk[c][c]));
-      else if (i < c) {
-        double2 s = make_double2(0.0, 0.0);
-        for (int k = i + 1; k <= c; ++k) s = cfnms(s, ld2(blk[i][k]), ld2(inv[k][c]));
-        x = cmul(s, crecip(ld2(blk[i][i])));
-      }
-      st2(inv[i][c], x);
-    }
-  }
-  __syncthreads();
-  for (int idx = tid; idx < W * W; idx += T) tU[idx] = ld2(inv[idx / W][idx % W]);
 }
 
-// ------------------------------------------------------------------ tile kernels
+// ------------------------------------------------------------------ products and triangular leaves
 
-template <int W>
-struct LuTiles {
-  static constexpr int TB = W < 16 ? 16 : W;  // rows of a row-block tile (MFMA needs 16)
-  // tall tile of the panel update: 64 rows x TB columns
-  using Upd = TileCfg<64, TB, 16, (TB == 32 ? 2 : 4), (TB == 32 ? 2 : 1)>;
-  // wide tile of the row block / back substitution: TB rows x 64 columns
-  using Row = TileCfg<TB, 64, 16, (TB == 32 ? 2 : 1), (TB == 32 ? 2 : 4)>;
-};
-
-template <class T>
-constexpr int lds_need() {
-  return T::LDS_DOUBLES > tri_lds_doubles<T>() ? T::LDS_DOUBLES : tri_lds_doubles<T>();
-}
+using LuTile = TileCfg<64, 64, 16, 2, 2>;
 
 __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
   for (int i = threadIdx.x; i < n; i += blockDim.x) sperm[i] = perm[i];
   __syncthreads();
 }
 
-// A[r0:n, r0:r0+w] -= L[r0:n, 0:r0] * U[0:r0, r0:r0+w]
-template <int W>
-__global__ void __launch_bounds__(LuTiles<W>::Upd::NT) k_panel_update(LuArgs a, int r0) {
-  using T = typename LuTiles<W>::Upd;
+// M[r][c] -= sum_{k in [k_lo, k_hi)} M[r][k] M[k][c] for logical rows [r_lo, r_hi), columns [c_lo, c_hi)
+__global__ void __launch_bounds__(LuTile::NT) k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
+                                                         int k_hi) {
+  using T = LuTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sperm[kLuMaxN];
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
   load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
-  const int w = min(W, a.n - r0);
-  const int m0 = r0 + blockIdx.x * T::BM;
+  const int tc = cdiv(c_hi - c_lo, T::BN);
+  const int m0 = r_lo + (blockIdx.x / tc) * T::BM, n0 = c_lo + (blockIdx.x % tc) * T::BN;
   Acc<T> acc;
   acc.zero();
   LdRowPerm la{M, a.ldm, sperm};
   LdRowPerm lb{M, a.ldm, sperm};
-  mma_loop<T>(la, lb, m0, a.n, r0, r0 + w, 0, r0, acc, lds);
+  mma_loop<T>(la, lb, m0, r_hi, n0, c_hi, k_lo, k_hi, acc, lds);
   acc_foreach<T>(acc, [&](int r, int c, double2 val) {
-    const int gr = m0 + r, gc = r0 + c;
-    if (gr < a.n && c < w) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < r_hi && gc < c_hi) {
       double2 *p = M + (long)sperm[gr] * a.ldm + gc;
       *p = csub(*p, val);
     }
   });
 }
 
-// Row block of panel p: rows [r0, r0+w), columns [r0+w, n+nrhs)
-template <int W>
-__global__ void __launch_bounds__(LuTiles<W>::Row::NT) k_row_block(LuArgs a, int r0, int p) {
-  using T = typename LuTiles<W>::Row;
-  __shared__ double lds[lds_need<T>()];
-  __shared__ int sperm[kLuMaxN];
+// In-tile triangular solve T x = c for the 64 columns of a staged tile, by substitution (LAPACK's
+// triangular-solve arithmetic).  Each wave owns 16 columns; 4 lanes share a column and each keeps the
+// rows j = part (mod 4), so a row step is a 4-lane partial dot product and two cross-lane additions.
+//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1);
+//   kUpper: false = unit lower (forward), true = upper with diagonal (backward); w <= W live rows.
+// out(i, col, x) receives every solved element of the rows i < w.
+template <int W, int kCP, bool kUpper, class Out>
+__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1], int w,
+                                          Out &&out) {
+  constexpr int NX = (W + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = wave * 16 + (lane >> 2), part = lane & 3;
+  double2 x[NX];
+#pragma unroll
+  for (int t = 0; t < NX; ++t) x[t] = make_double2(0.0, 0.0);
+#pragma unroll 1
+  for (int step = 0; step < w; ++step) {
+    const int i = kUpper ? w - 1 - step : step;
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int j = part + 4 * t;
+      const bool use = kUpper ? (j > i && j < w) : (j < i);
+      const double lx = use ? tri[i][j].x : 0.0, ly = use ? tri[i][j].y : 0.0;
+      ax += lx * x[t].x - ly * x[t].y;
+      ay += lx * x[t].y + ly * x[t].x;
+    }
+    ax += __shfl_xor(ax, 1);
+    ay += __shfl_xor(ay, 1);
+    ax += __shfl_xor(ax, 2);
+    ay += __shfl_xor(ay, 2);
+    if (part == (i & 3)) {
+      double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
+      if (kUpper) v = cmul(v, crecip(ld2(tri[i][i])));  // scaled reciprocal: no overflow of |u|^2
+      const int ti = i >> 2;
+#pragma unroll
+      for (int t = 0; t < NX; ++t) {
+        x[t].x = (t == ti) ? v.x : x[t].x;
+        x[t].y = (t == ti) ? v.y : x[t].y;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NX; ++t) {
+    const int j = part + 4 * t;
+    if (j < w) out(j, col, x[t]);
+  }
+}
+
+// Leaf of the triangular solves: rows [r0, r0+w) of columns [c_lo, c_hi), in place, with the W x W
+// diagonal block at logical rows/columns r0 (unit lower if !kUpper, upper otherwise).
+template <int W, bool kUpper>
+__global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, int c_hi) {
+  constexpr int CP = 64 + 1;
+  __shared__ double cr[W * CP], ci[W * CP];
+  __shared__ double2 tri[W][W + 1];
+  __shared__ int sp[W];
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
-  load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
+  const int *perm = a.perm + (long)mat * a.sP;
   const int w = min(W, a.n - r0);
-  const int ncol = a.n + a.nrhs;
-  const int c0 = r0 + w + blockIdx.x * T::BN;
-  Acc<T> acc;
-  acc.zero();
-  LdRowPerm la{M, a.ldm, sperm};
-  LdRowPerm lb{M, a.ldm, sperm};
-  mma_loop<T>(la, lb, r0, r0 + w, c0, ncol, 0, r0, acc, lds);
-  const double2 *tL = a.tri + (long)mat * a.sT + (long)p * 2 * W * W;
-  LdRow lt{tL, W};
-  tri_apply<T>(lt, W, acc,
-               [&](int r, int c, double2 val) {
-                 if (r < w && c0 + c < ncol) return csub(M[(long)sperm[r0 + r] * a.ldm + c0 + c], val);
-                 return make_double2(0.0, 0.0);
-               },
-               lds);
-  acc_foreach<T>(acc, [&](int r, int c, double2 val) {
-    if (r < w && c0 + c < ncol) M[(long)sperm[r0 + r] * a.ldm + c0 + c] = val;
+  const int c0 = c_lo + blockIdx.x * 64;
+  if (threadIdx.x < W) sp[threadIdx.x] = threadIdx.x < w ? perm[r0 + threadIdx.x] : 0;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W * 64; idx += 256) {
+    const int i = idx / 64, c = idx % 64;
+    const double2 v = (i < w && c0 + c < c_hi) ? M[(long)sp[i] * a.ldm + c0 + c] : make_double2(0.0, 0.0);
+    cr[i * CP + c] = v.x;
+    ci[i * CP + c] = v.y;
+  }
+  for (int idx = threadIdx.x; idx < W * W; idx += 256) {
+    const int i = idx / W, j = idx % W;
+    st2(tri[i][j], (i < w && j < w) ? M[(long)sp[i] * a.ldm + r0 + j] : make_double2(0.0, 0.0));
+  }
+  __syncthreads();
+  tile_trsm<W, CP, kUpper>(cr, ci, tri, w, [&](int i, int col, double2 v) {
+    if (c0 + col < c_hi) M[(long)sp[i] * a.ldm + c0 + col] = v;
   });
 }
 
-// Back substitution of block row p: X[r0:r0+w, :] = U11^{-1} (Y[r0:r0+w, :] - U[r0:r0+w, r0+w:n] X[r0+w:n, :])
-template <int W>
-__global__ void __launch_bounds__(LuTiles<W>::Row::NT) k_back_sub(LuArgs a, int r0, int p) {
-  using T = typename LuTiles<W>::Row;
-  __shared__ double lds[lds_need<T>()];
-  __shared__ int sperm[kLuMaxN];
+// X[r][c] = M[perm[r]][n + c]: the solution rows in natural order
+__global__ void k_copy_out(LuArgs a) {
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
-  double2 *M = a.M + (long)mat * a.sM;
+  const double2 *M = a.M + (long)mat * a.sM;
+  const int *perm = a.perm + (long)mat * a.sP;
   double2 *X = a.X + (long)mat * a.sX;
-  load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
-  const int w = min(W, a.n - r0);
-  const int c0 = blockIdx.x * T::BN;
-  Acc<T> acc;
-  acc.zero();
-  LdRowPerm la{M, a.ldm, sperm};
-  LdRow lb{X, a.ldx};
-  mma_loop<T>(la, lb, r0, r0 + w, c0, a.nrhs, r0 + w, a.n, acc, lds);
-  const double2 *tU = a.tri + (long)mat * a.sT + (long)p * 2 * W * W + W * W;
-  LdRow lt{tU, W};
-  tri_apply<T>(lt, W, acc,
-               [&](int r, int c, double2 val) {
-                 if (r < w && c0 + c < a.nrhs)
-                   return csub(M[(long)sperm[r0 + r] * a.ldm + a.n + c0 + c], val);
-                 return make_double2(0.0, 0.0);
-               },
-               lds);
-  acc_foreach<T>(acc, [&](int r, int c, double2 val) {
-    if (r < w && c0 + c < a.nrhs) X[(long)(r0 + r) * a.ldx + c0 + c] = val;
-  });
+  const long total = (long)a.n * a.nrhs;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int r = idx / a.nrhs, c = idx % a.nrhs;
+    X[(long)r * a.ldx + c] = M[(long)perm[r] * a.ldm + a.n + c];
+  }
 }
 
 // ------------------------------------------------------------------ driver
 
 template <int W, int R, int LB>
-static ss_status lu_run(ss_ctx *ctx, const LuDesc &d) {
-  const LuArgs a = make_args(d);
-  const int n = d.n, np = cdiv(n, W), ncol = d.n + d.nrhs;
-  for (int p = 0; p < np; ++p) {
-    const int r0 = p * W, w = std::min(W, n - r0);
-    if (p > 0) {
-      dim3 g(cdiv(n - r0, LuTiles<W>::Upd::BM), d.nmat);
-      {
-        KernelScope ks_(ctx, "panel_update");
-        hipLaunchKernelGGL(k_panel_update<W>, g, dim3(LuTiles<W>::Upd::NT), 0, ctx->stream, a, r0);
-      }
-    }
-    const int rows = cdiv(n - r0, R);
-    const int threads = std::min(LB, std::max(64, cdiv(rows, 64) * 64));
-    {
+struct LuRun {
+  ss_ctx *ctx;
+  const LuDesc &d;
+  LuArgs a;
+
+  // split point: a multiple of W strictly inside (lo, hi)
+  int mid(int lo, int hi) const { return lo + std::max(W, ((hi - lo) / 2 + W - 1) / W * W); }
+
+  void gemm(int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int k_hi) {
+    if (r_lo >= r_hi || c_lo >= c_hi || k_lo >= k_hi) return;
+    const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
+    KernelScope ks_(ctx, "lu_gemm");
+    hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi, c_lo, c_hi,
+                       k_lo, k_hi);
+  }
+  template <bool kUpper>
+  void leaf(int r0, int c_lo, int c_hi) {
+    if (c_lo >= c_hi) return;
+    KernelScope ks_(ctx, "trsm");
+    hipLaunchKernelGGL((k_trsm_leaf<W, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream, a,
+                       r0, c_lo, c_hi);
+  }
+  // unit lower solve on rows [lo, hi) of columns [c_lo, c_hi)
+  void trsm_lower(int lo, int hi, int c_lo, int c_hi) {
+    if (hi - lo <= W) return leaf<false>(lo, c_lo, c_hi);
+    const int m = mid(lo, hi);
+    trsm_lower(lo, m, c_lo, c_hi);
+    gemm(m, hi, c_lo, c_hi, lo, m);
+    trsm_lower(m, hi, c_lo, c_hi);
+  }
+  // upper solve on rows [lo, hi) of columns [c_lo, c_hi)
+  void trsm_upper(int lo, int hi, int c_lo, int c_hi) {
+    if (hi - lo <= W) return leaf<true>(lo, c_lo, c_hi);
+    const int m = mid(lo, hi);
+    trsm_upper(m, hi, c_lo, c_hi);
+    gemm(lo, m, c_lo, c_hi, m, hi);
+    trsm_upper(lo, m, c_lo, c_hi);
+  }
+  void factor(int c0, int c1) {
+    if (c1 - c0 <= W) {
+      const int rows = cdiv(d.n - c0, R);
+      const int threads = std::min(LB, std::max(64, cdiv(rows, 64) * 64));
       KernelScope ks_(ctx, "panel");
-      hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, r0, p);
+      hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+      return;
     }
-    const int right = ncol - (r0 + w);
-    if (right > 0) {
-      dim3 g(cdiv(right, LuTiles<W>::Row::BN), d.nmat);
-      {
-        KernelScope ks_(ctx, "row_block");
-        hipLaunchKernelGGL(k_row_block<W>, g, dim3(LuTiles<W>::Row::NT), 0, ctx->stream, a, r0, p);
-      }
-    }
+    const int cm = mid(c0, c1);
+    factor(c0, cm);
+    trsm_lower(c0, cm, cm, c1);
+    gemm(cm, d.n, cm, c1, c0, cm);
+    factor(cm, c1);
   }
-  if (d.nrhs > 0) {
-    for (int p = np - 1; p >= 0; --p) {
-      const int r0 = p * W;
-      dim3 g(cdiv(d.nrhs, LuTiles<W>::Row::BN), d.nmat);
-      {
-        KernelScope ks_(ctx, "back_sub");
-        hipLaunchKernelGGL(k_back_sub<W>, g, dim3(LuTiles<W>::Row::NT), 0, ctx->stream, a, r0, p);
-      }
+  ss_status run() {
+    factor(0, d.n);
+    if (d.nrhs > 0) {
+      trsm_lower(0, d.n, d.n, d.n + d.nrhs);
+      trsm_upper(0, d.n, d.n, d.n + d.nrhs);
+      const long total = (long)d.n * d.nrhs;
+      const int blocks = (int)std::min<long>((total + 255) / 256, 256);
+      hipLaunchKernelGGL(k_copy_out, dim3(blocks, d.nmat), dim3(256), 0, ctx->stream, a);
     }
+    return check_launch(ctx, "lu_solve");
   }
-  return check_launch(ctx, "lu_solve");
-}
+};
 
 ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_solve: order out of range");
   const int W = lu_panel_width(d.n);
-  if (W == 32) return lu_run<32, 1, 512>(ctx, d);
-  if (W == 16) return lu_run<16, 1, 1024>(ctx, d);
-  return lu_run<8, 2, 1024>(ctx, d);
+  if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run();
+  if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run();
+  return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run();
 }
 
 ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d) {

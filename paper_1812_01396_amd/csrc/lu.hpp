@@ -17,8 +17,6 @@ struct LuDesc {
   int ldm = 0;
   int *perm = nullptr;  // [nmat][n]
   long sP = 0;
-  double2 *tri = nullptr;  // [nmat][npanel][2][W][W]: inverses of the diagonal blocks of L and U
-  long sT = 0;
   int *zp = nullptr;  // [nmat]: 1 + first column with an exactly zero pivot, 0 if none
   double2 *X = nullptr;
   long sX = 0;
@@ -30,8 +28,6 @@ struct LuDesc {
 
 // Panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to 2048).
 int lu_panel_width(int n);
-// Elements (double2) of `tri` needed per system.
-long lu_tri_elems(int n);
 // Largest order supported.
 constexpr int kLuMaxN = 2048;
 

@@ -163,10 +163,9 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
                     const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
   const long ss2 = (long)s * s;
   const int n = 2 * s, nrhs = 2 * s + m, ldm = 4 * s + m;
-  void *wM, *wP, *wT, *wZ, *wO;
+  void *wM, *wP, *wZ, *wO;
   SS_TRY(workspace(ctx, kSlotM, sizeof(double2) * (size_t)batch * n * ldm, &wM));
   SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * (size_t)batch * n, &wP));
-  SS_TRY(workspace(ctx, kSlotTri, sizeof(double2) * (size_t)batch * lu_tri_elems(n), &wT));
   SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)batch, &wZ));
   SS_TRY(workspace(ctx, kSlotObc, sizeof(double2) * (size_t)batch * (4 * ss2 + (long)n * nrhs), &wO));
   ObcArgs a;
@@ -204,8 +203,6 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
   d.ldm = ldm;
   d.perm = (int *)wP;
   d.sP = n;
-  d.tri = (double2 *)wT;
-  d.sT = lu_tri_elems(n);
   d.zp = (int *)wZ;
   d.X = a.X;
   d.sX = (long)n * nrhs;

@@ -309,11 +309,10 @@ ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *
   if (tol <= 0) tol = 1e-14;
   if (max_iter <= 0) max_iter = 200;
   // workspace: state 7 s^2 + M 3 s^2 + Y 2 s^2 per instance; final solves reuse M/Y (2 x 2 s^2 each)
-  void *wD, *wP, *wT, *wZ, *wMisc;
+  void *wD, *wP, *wZ, *wMisc;
   const size_t per = (size_t)12 * ss2;
   SS_TRY(workspace(ctx, kSlotDec, sizeof(double2) * per * batch, &wD));
   SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * (size_t)2 * batch * s, &wP));
-  SS_TRY(workspace(ctx, kSlotTri, sizeof(double2) * (size_t)2 * batch * lu_tri_elems(s), &wT));
   SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)2 * batch, &wZ));
   const size_t misc_bytes = (size_t)batch * (2 * 8 + 8 + 4 + 4 + 4) + 64 + (size_t)batch * 4 * 8;
   SS_TRY(workspace(ctx, kSlotMisc, misc_bytes, &wMisc));
@@ -362,8 +361,6 @@ ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *
   d.ldm = 3 * s;
   d.perm = (int *)wP;
   d.sP = s;
-  d.tri = (double2 *)wT;
-  d.sT = lu_tri_elems(s);
   d.zp = a.zp;
   d.X = a.Y;
   d.sX = 2 * ss2;

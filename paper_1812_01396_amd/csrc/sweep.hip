@@ -182,10 +182,9 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   const int s = hs->s, nb = hs->nb, nmat = 2 * batch;
   const long ss2 = (long)s * s;
   const int n = s, nrhs = s, ldm = 2 * s;
-  void *wM, *wP, *wT, *wZ, *wX, *wC;
+  void *wM, *wP, *wZ, *wX, *wC;
   SS_TRY(workspace(ctx, kSlotM, sizeof(double2) * nmat * (size_t)n * ldm, &wM));
   SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * nmat * (size_t)n, &wP));
-  SS_TRY(workspace(ctx, kSlotTri, sizeof(double2) * nmat * (size_t)lu_tri_elems(n), &wT));
   SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)(nmat + batch), &wZ));
   SS_TRY(workspace(ctx, kSlotX, sizeof(double2) * nmat * (size_t)nb * ss2, &wX));
   wC = (int *)wZ + nmat;
@@ -220,8 +219,6 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   d.ldm = ldm;
   d.perm = a.perm;
   d.sP = n;
-  d.tri = (double2 *)wT;
-  d.sT = lu_tri_elems(n);
   d.zp = a.zp;
   d.sX = (long)nb * ss2;
   d.ldx = s;

@@ -211,68 +211,4 @@ __device__ __forceinline__ void acc_foreach(const Acc<T> &acc, F &&f) {
       }
 }
 
-// Second product inside the tile: out = Tri * C where Tri is a K x K block (K <= BM, given as a
-// loader over [0, K) x [0, K)) and C is the BM x BN tile held in `acc`, transformed element-wise by
-// `pre(r, c, v)` before the product.  Used to apply an inverted triangular diagonal block to the
-// rows of a tile.  Result returned in `acc` (rows >= K are zero).
-template <class T, class LT, class Pre>
-__device__ __forceinline__ void tri_apply(const LT &tri, int K, Acc<T> &acc, Pre &&pre, double *lds) {
-  static_assert(T::BK >= 4, "");
-  Lds<T> L(lds);
-  // stage the tile as the B operand [k = tile row][n = tile col]; needs BM rows of B planes
-  // (the engine's B planes hold BK rows; use the A planes' storage for the overflow when BM > BK)
-  double *cr = lds;                        // [BM][PB]
-  double *ci = lds + T::BM * T::PB;        // [BM][PB]
-  double *tr = ci + T::BM * T::PB;         // [BM][PA]  tri^T planes: tr[k][m] = tri(m, k)
-  double *ti = tr + T::BM * T::PA;
-  __syncthreads();
-  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
-    double2 w = pre(r, c, v);
-    cr[r * T::PB + c] = w.x;
-    ci[r * T::PB + c] = w.y;
-  });
-  for (int idx = threadIdx.x; idx < T::BM * T::BM; idx += T::NT) {
-    const int m = idx / T::BM, k = idx % T::BM;
-    double2 v = (m < K && k < K) ? tri(m, k) : make_double2(0.0, 0.0);
-    tr[k * T::PA + m] = v.x;
-    ti[k * T::PA + m] = v.y;
-  }
-  __syncthreads();
-  acc.zero();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave % T::WM, wn = wave / T::WM;
-  const int mbase = wm * T::FM * 16 + (lane & 15);
-  const int nbase = wn * T::FN * 16 + (lane & 15);
-  for (int ks = 0; ks < T::BM / 4; ++ks) {
-    const int kr = ks * 4 + (lane >> 4);
-    double ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
-#pragma unroll
-    for (int i = 0; i < T::FM; ++i) {
-      ar[i] = tr[kr * T::PA + mbase + i * 16];
-      ai[i] = ti[kr * T::PA + mbase + i * 16];
-      an[i] = -ai[i];
-    }
-#pragma unroll
-    for (int j = 0; j < T::FN; ++j) {
-      br[j] = cr[kr * T::PB + nbase + j * 16];
-      bi[j] = ci[kr * T::PB + nbase + j * 16];
-    }
-#pragma unroll
-    for (int i = 0; i < T::FM; ++i)
-#pragma unroll
-      for (int j = 0; j < T::FN; ++j) {
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], acc.re[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc.im[i][j], 0, 0, 0);
-      }
-  }
-  (void)L;
-}
-
-template <class T>
-constexpr int tri_lds_doubles() {
-  return 2 * T::BM * T::PB + 2 * T::BM * T::PA;
-}
-
 }  // namespace ss

@@ -135,6 +135,15 @@ def test_first_last_columns_are_inverse_columns(nb, s):
     assert np.linalg.norm(q - ref) <= 1e-11 * np.linalg.norm(ref)
 
 
+def test_mirrored_columns_against_dense():
+    inst = synth.random_btd(5, 4, seed=61)
+    ad, au, al, a = _dense(inst, 0.11)
+    q = transport.first_last_columns_mirrored(ad, au, al)
+    inv = np.linalg.inv(a)
+    ref = np.concatenate([inv[:, :4], inv[:, -4:]], axis=1).reshape(5, 4, 8)
+    assert np.linalg.norm(q - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
 @pytest.mark.parametrize("nb,s", [(1, 4), (4, 5), (7, 3)])
 def test_corner_greens_and_psi_against_dense(nb, s):
     inst = synth.random_btd(nb, s, seed=20 + nb)
@@ -298,3 +307,28 @@ def test_golden_chain16_channels_match_oracle_transmission():
     for E, nch, _gap in rows[::7]:
         out = _solve(inst, E)
         assert abs(out["t_lr"] - nch) < 1e-8
+
+
+def test_decimation_conditioning_pins():
+    """The conditioning estimate used for tolerances: exactly 1 for a one-orbital chain, and for a
+    decoupled ladder equal to the worst ratio over the passes of the scalar chains' bulk energies
+    (each chain decimated on its own in scalar arithmetic)."""
+    cell = synth.scalar_chain_cell(0.2, 1.0)
+    a0, a1, am1 = selfenergy.lead_blocks(*cell, 0.4, 1e-8)
+    assert selfenergy.decimation_conditioning(a0, a1, am1) == pytest.approx(1.0)
+    eps0 = np.array([-0.5, 0.3, 1.1])
+    t = np.array([0.4, 0.9, 0.7])
+    E, eta = 0.25, 1e-6
+    a0, a1, am1 = selfenergy.lead_blocks(*synth.ladder_cell(eps0, t), E, eta)
+    est = selfenergy.decimation_conditioning(a0, a1, am1)
+    # scalar recursions e <- e - 2 a b / e, a <- -a^2/e, b <- -b^2/e per chain
+    e = (E + 1j * eta) - eps0
+    al = t.astype(complex)
+    be = t.astype(complex)
+    worst = 1.0
+    for _ in range(200):
+        worst = max(worst, np.max(np.abs(e)) / np.min(np.abs(e)))
+        e, al, be = e - 2 * al * be / e, -al * al / e, -be * be / e
+        if np.max(np.abs(al)) + np.max(np.abs(be)) <= 1e-14 * np.max(np.abs((E + 1j * eta) - eps0)):
+            break
+    assert est == pytest.approx(worst, rel=1e-8)
