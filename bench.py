@@ -6,10 +6,15 @@ lead self-energies (decimation), Q = first/last block columns of (E S - H)^{-1} 
 pivoted LU), the 2s x 2s open-boundary correction with psi for m injected columns and the corner of
 G^R, and the Caroli transmission T_LR, T_RL.
 
+Modes: fp64 (plain SplitSolve in FP64, T from the corner of G^R) and mixed (recursion products in
+FP32 on the matrix cores, FP64 LU, injection b' = [W_L; 0] from the left lead, FP64 iterative
+refinement of psi on the full open system, T from the refined psi).
+
 Workloads (synthetic, seeded; see synth/):
   dft512   s = 512 (8x8x8 lattice slab), nb = 40, 64 energies in [-5, 5] eV x 4 momenta
            k in {pi/8, 3pi/8, 5pi/8, 7pi/8}, seed 1, crystal device, complex128   (default)
   chain16  s = 16 random chain cell, nb = 32, 64 energies in [-3, 3], seed 0, complex128
+  dft1024  s = 1024 (8x8x16 slab), nb = 60, 32 energies in [-5, 5] eV, k = pi/3, seed 2
 
 Prints one JSON line.  --gpus > 1 is refused: this build measures one GPU.
 """
@@ -34,7 +39,9 @@ WORKLOADS = {
     "dft512": dict(s=512, nb=40, n_e=64, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8],
                    seed=1, eta=1e-8, m=32, chunk=64),
     "chain16": dict(s=16, nb=32, n_e=64, e_lo=-3.0, e_hi=3.0, ks=[0.0], seed=0, eta=1e-8, m=4, chunk=64),
+    "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=16),
 }
+FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
 
 
 def sweep_flops(nb: int, s: int) -> float:
@@ -109,12 +116,14 @@ class Pipeline:
     of G^R, and T.  Outputs stay on the device (sigma, iters, resid, psi, gc, T, info_*).
     """
 
-    def __init__(self, workload: str, chunk: int = 0):
+    def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-12):
         import torch
 
         import paper_1812_01396_amd as ss
 
         self.ss, self.torch = ss, torch
+        self.mode = mode
+        self.refine_tol = refine_tol
         w, insts, E_np, kidx_np, inj_np = build_inputs(workload)
         self.w, self.insts, self.E_np, self.kidx_np, self.inj_np = w, insts, E_np, kidx_np, inj_np
         s, nb, m = w["s"], w["nb"], w["m"]
@@ -144,6 +153,10 @@ class Pipeline:
         self.T = torch.empty(nb_inst, 2, dtype=torch.float64, device=dev)
         self.info_q = torch.empty(nb_inst, dtype=torch.int32, device=dev)
         self.info_o = torch.empty(nb_inst, dtype=torch.int32, device=dev)
+        self.T_psi = torch.empty(nb_inst, dtype=torch.float64, device=dev)
+        self.rank = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
+        self.ir_iters = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
+        self.ir_resid = torch.zeros(nb_inst, dtype=torch.float64, device=dev)
         self.stream_main = torch.cuda.current_stream(dev)
         self.stream_sig = torch.cuda.Stream(dev)  # default priority
         self.ctx = ss.Context(0, self.stream_main)
@@ -170,19 +183,29 @@ class Pipeline:
 
         th = threading.Thread(target=run_sigma)
         th.start()
+        mixed = self.mode == "mixed"
         for c0 in range(0, self.n, self.chunk):
             c1 = min(c0 + self.chunk, self.n)
             q = self.Qbuf[: c1 - c0]
             ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
-                                     kidx=self.kidx[c0:c1], Q=q, info=self.info_q[c0:c1], validate=False)
+                                     kidx=self.kidx[c0:c1], Q=q, info=self.info_q[c0:c1], validate=False,
+                                     prec=ss.SS_PREC_FP32 if mixed else ss.SS_PREC_FP64, keep_factors=mixed)
             if c0 == 0:
                 th.join()
                 if err:
                     raise err[0]
                 self.stream_main.wait_event(done)
-            ss.ss_apply_obc(self.ctx, q, self.sigma[c0:c1], inj=self.inj[c0:c1], psi=self.psi[c0:c1],
-                            gc=self.gc[c0:c1], info=self.info_o[c0:c1])
-            ss.ss_transmission(self.ctx, self.gc[c0:c1], self.sigma[c0:c1], T=self.T[c0:c1])
+            sig = self.sigma[c0:c1]
+            if mixed:
+                ss.ss_injection_left(self.ctx, sig, w["m"], inj=self.inj[c0:c1], rank=self.rank[c0:c1])
+            ss.ss_apply_obc(self.ctx, q, sig, inj=self.inj[c0:c1], psi=self.psi[c0:c1], gc=self.gc[c0:c1],
+                            info=self.info_o[c0:c1])
+            if mixed:
+                ss.ss_refine_psi(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1], q, sig,
+                                 self.inj[c0:c1], self.psi[c0:c1], kidx=self.kidx[c0:c1], tol=self.refine_tol,
+                                 iters=self.ir_iters[c0:c1], resid=self.ir_resid[c0:c1])
+                ss.ss_transmission_psi(self.ctx, self.psi[c0:c1], sig, T=self.T_psi[c0:c1])
+            ss.ss_transmission(self.ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
 
 
 def main():
@@ -191,6 +214,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS))
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
     ap.add_argument("--roofline-kernel", default="dec_update",
                     help="kernel family timed with HIP events for the roofline entry")
@@ -205,7 +229,7 @@ def main():
 
     import torch
 
-    pipe = Pipeline(args.workload, args.chunk)
+    pipe = Pipeline(args.workload, args.chunk, args.mode)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel
     timed_ctx = pipe.ctx_s if fam in ("dec_update",) else pipe.ctx
@@ -223,7 +247,11 @@ def main():
     timed_ctx.kernel_timer(None)
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
+    mixed = args.mode == "mixed"
+    # the product's T: Caroli (T_LR, T_RL) in fp64 mode; T carried by the refined psi in mixed mode
     T_np = pipe.T.cpu().numpy()
+    if mixed:
+        T_np = np.stack([pipe.T_psi.cpu().numpy()] * 2, axis=1)
     bad = int((pipe.info_s.cpu() != 0).sum() + (pipe.info_q.cpu() != 0).sum() + (pipe.info_o.cpu() != 0).sum())
     ms_per_step = elapsed * 1e3 / args.steps
     value = nbatch * args.steps / elapsed
@@ -238,8 +266,9 @@ def main():
     roof = None
     if k_launches > 0 and fam in fam_flops:
         achieved = fam_flops[fam] / (k_ms * 1e-3) / 1e12
-        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                    frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None, kernel=fam,
+        peak = FP32_PEAK_TFLOPS if (mixed and fam in ("form", "chain")) else FP64_PEAK_TFLOPS
+        roof = dict(bound="mfma", achieved=round(achieved, 3), peak=peak, unit="TFLOP/s",
+                    frac=round(achieved / peak, 4), traffic=None, kernel=fam,
                     launches=int(k_launches), avg_launch_ms=round(k_ms / k_launches, 4))
 
     cpu = None
@@ -262,11 +291,15 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "s": s, "nb": nb, "instances": nbatch, "energies": w["n_e"],
                    "k_points": len(w["ks"]), "m_inj": m, "eta": w["eta"], "chunk": pipe.chunk,
-                   "precision": "fp64"},
+                   "precision": args.mode},
         "tflops_step": round(f_step / (ms_per_step * 1e-3) / 1e12, 3),
         "frac_fp64_peak_step": round(f_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
         "decimation_iters": [int(it_np.min()), int(it_np.max()), round(float(it_np.mean()), 2)],
         "nonzero_info": bad,
+        "t_lr_minus_t_rl_max": float(np.abs(pipe.T.cpu().numpy()[:, 0] - pipe.T.cpu().numpy()[:, 1]).max()),
+        "refine_iters": ([int(pipe.ir_iters.min()), int(pipe.ir_iters.max())] if mixed else None),
+        "refine_resid_max": (float(pipe.ir_resid.max()) if mixed else None),
+        "injection_rank": ([int(pipe.rank.min()), int(pipe.rank.max())] if mixed else None),
         "roofline": roof,
         "cpu_baseline": cpu,
         "t_err_vs_oracle": t_err,

@@ -64,6 +64,11 @@ ss_status ss_create(ss_ctx **ctx, int device, void *hip_stream);
 void ss_destroy(ss_ctx *ctx);
 /* Redirect later calls to another stream of the same device. */
 ss_status ss_set_stream(ss_ctx *ctx, void *hip_stream);
+/* on != 0: calls never wait for the stream (required inside stream/graph capture).  Iterative loops
+ * then enqueue all of their passes (max_iter) and converged instances skip the work of later passes.
+ * Workspaces must already be large enough (run the same calls once eagerly first): growing a
+ * workspace waits for the stream, and the call then fails with SS_ERR_ARG instead. */
+ss_status ss_set_sync_free(ss_ctx *ctx, int on);
 /* Block the host until the context's stream has drained. */
 ss_status ss_synchronize(ss_ctx *ctx);
 /* Static text for a status code, and the detail of the context's last failure ("" if none). */
@@ -118,19 +123,29 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
                              const int *kidx, const double *E, double eta, double tol,
                              int max_iter, ss_c128 *sigma, int *iters, double *resid, int *info);
 
+/* Precision of the recursion's block products in ss_precompute_columns.  The LU factorizations, the
+ * triangular solves, the corner system and every residual are always FP64. */
+#define SS_PREC_FP64 0 /* complex FP64 products (FP64 matrix cores)                           */
+#define SS_PREC_FP32 1 /* complex FP32 products with FP32 accumulation, FP64 storage            */
+
+/* flags of ss_precompute_columns */
+#define SS_KEEP_FACTORS 1 /* keep the first-column recursion's factors in the context for     */
+                          /* ss_refine_psi (valid until the next ss_precompute_columns call)    */
+
 /* Step 1 (Sec. 3B, Alg. 1): Q = [A^{-1}_{:,1}, A^{-1}_{:,n_B}] for A = E*S - H.
  *
  * Backward recursion X_{n_B+1} = 0, (A_{i,i} - A_{i,i+1} X_{i+1}) X_i = A_{i,i-1} with A_{1,0} := I,
  * then Q_i = -X_i Q_{i-1} from Q_0 = -I, gives the first block column; the mirrored recursion (from
  * block 1 upwards with A_{n_B,n_B+1} := I) gives the last one.  Each diagonal system is solved by LU
- * with partial pivoting on the GPU.
+ * with partial pivoting on the GPU.  prec: SS_PREC_FP64 or SS_PREC_FP32 (see above); flags: 0 or
+ * SS_KEEP_FACTORS.
  *
  * Output Q [batch][nb][s][2s]: block row i holds (A^{-1})_{i,1} in columns [0, s) and
  * (A^{-1})_{i,n_B} in columns [s, 2s).  info [batch] (may be NULL): 0, or 1 + (i-1)*s + c for an
  * exactly zero pivot in column c of the i-th diagonal system (1-based i; the smallest such code over
  * both recursions). */
 ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx,
-                                const double *E, ss_c128 *Q, int *info);
+                                const double *E, int prec, int flags, ss_c128 *Q, int *info);
 
 /* Steps 2-4 (Sec. 3B, Eq. (x)): fold the boundary self-energies in and recover the wave function.
  *
@@ -152,6 +167,33 @@ ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q,
  * Output T [batch][2] = (T_LR, T_RL). */
 ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
                           double *T);
+
+/* Injection from the left lead (Sec. 3A: Inj is built from the lead's modes; here from its
+ * broadening).  For each instance, a pivoted Cholesky factorization Gamma_L ~ W_L W_L^H of
+ * Gamma_L = i (Sigma_L - Sigma_L^H) stops when the largest remaining diagonal entry falls to
+ * tol * max_i Gamma_L[i][i] (tol <= 0 means 1e-12) or after mmax columns; b' = [W_L; 0] is written to
+ * inj [batch][2s][mmax] (unused columns are zero) and the number of columns kept to rank [batch]
+ * (may be NULL).  Injecting b' gives psi whose last block row carries the transmission:
+ * T = Tr[psi_nb^H Gamma_R psi_nb] (ss_transmission_psi). */
+ss_status ss_injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, double tol, int mmax,
+                            ss_c128 *inj, int *rank);
+
+/* Iterative refinement of psi on the full open system (Sec. 3B, Eq. (x) applied to a residual):
+ *     r = B b' - (A - B C) psi   (FP64),   psi += A~^{-1} r + Q R^{-1} C A~^{-1} r,
+ * where A~^{-1} uses the factors kept by the last ss_precompute_columns(..., SS_KEEP_FACTORS) on this
+ * context (the same hs, batch, kidx and E) and R^{-1} the corner factorization of the last
+ * ss_apply_obc on this context (no other call may run on the context in between).  Stops per instance
+ * when ||r||_F <= tol ||B b'||_F (tol <= 0 means 1e-12) or after max_iter passes (<= 0 means 10).
+ * psi [batch][nb][s][m] is updated in place; iters [batch] and resid [batch] (final relative
+ * residual) may be NULL. */
+ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                        const ss_c128 *Q, const ss_c128 *sigma, int m, const ss_c128 *inj,
+                        ss_c128 *psi, double tol, int max_iter, int *iters, double *resid);
+
+/* Transmission carried by a wave function injected from the left lead with b' = [W_L; 0]:
+ * T [batch] = Re Tr[psi_nb^H Gamma_R psi_nb] (psi [batch][nb][s][m], sigma [batch][2][s][s]). */
+ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi,
+                              const ss_c128 *sigma, double *T);
 
 #ifdef __cplusplus
 }

@@ -9,8 +9,13 @@ from .splitsolve import (  # noqa: F401
     Context,
     SplitSolveError,
     load_library,
+    SS_PREC_FP32,
+    SS_PREC_FP64,
     ss_apply_obc,
+    ss_injection_left,
     ss_lead_selfenergy,
     ss_precompute_columns,
+    ss_refine_psi,
     ss_transmission,
+    ss_transmission_psi,
 )

@@ -22,6 +22,8 @@ ss_status workspace(ss_ctx *ctx, Slot s, size_t bytes, void **out) {
   Buffer &b = ctx->slot[s];
   if (bytes == 0) bytes = 256;
   if (b.bytes < bytes) {
+    if (ctx->sync_free)
+      return fail(ctx, SS_ERR_ARG, "workspace too small in sync-free mode (run the call eagerly once first)");
     if (b.ptr) {
       if (hipStreamSynchronize(ctx->stream) != hipSuccess)
         return fail(ctx, SS_ERR_DEVICE, "workspace: stream synchronize before reallocation failed");
@@ -132,6 +134,12 @@ ss_status ss_set_stream(ss_ctx *ctx, void *hip_stream) {
   return SS_OK;
 }
 
+ss_status ss_set_sync_free(ss_ctx *ctx, int on) {
+  if (!ctx) return SS_ERR_ARG;
+  ctx->sync_free = on != 0;
+  return SS_OK;
+}
+
 ss_status ss_synchronize(ss_ctx *ctx) {
   SS_TRY(enter(ctx));
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
@@ -181,12 +189,13 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
   if (!H00 || !H01 || !S00 || !S01 || !E || !sigma)
     return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy: null input or output pointer");
   if (!(eta >= 0.0)) return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy: eta must be >= 0");
+  ctx->corner_valid = false;  // decimation reuses the corner system's workspace
   return lead_selfenergy(ctx, batch, s, nk, H00, H01, S00, S01, kidx, E, eta, tol, max_iter, sigma, iters, resid,
                          info);
 }
 
 ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
-                                ss_c128 *Q, int *info) {
+                                int prec, int flags, ss_c128 *Q, int *info) {
   SS_TRY(enter(ctx));
   if (!hs) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null structure");
   if (batch < 0 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
@@ -195,7 +204,11 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   if (batch == 0) return SS_OK;
   if (!hs->H_diag || !hs->S_diag || !E || !Q || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)))
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null input or output pointer");
-  return precompute_columns(ctx, hs, batch, kidx, E, Q, info);
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown precision");
+  if (flags & ~SS_KEEP_FACTORS) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown flags");
+  ctx->corner_valid = false;  // the recursion reuses the corner system's workspace
+  return precompute_columns(ctx, hs, batch, kidx, E, prec, flags, Q, info);
 }
 
 ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
@@ -206,7 +219,12 @@ ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, 
   if (batch == 0) return SS_OK;
   if (!Q || !sigma || (m > 0 && (!inj || !psi)))
     return fail(ctx, SS_ERR_ARG, "ss_apply_obc: null input or output pointer");
-  return apply_obc(ctx, batch, nb, s, Q, sigma, m, inj, psi, gc, info);
+  ss_status st = apply_obc(ctx, batch, nb, s, Q, sigma, m, inj, psi, gc, info);
+  ctx->corner_valid = st == SS_OK;
+  ctx->corner_batch = batch;
+  ctx->corner_s = s;
+  ctx->corner_ldm = 4 * s + m;
+  return st;
 }
 
 ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
@@ -216,6 +234,40 @@ ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, cons
   if (batch == 0) return SS_OK;
   if (!gc || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission: null pointer");
   return transmission(ctx, batch, s, gc, sigma, T);
+}
+
+ss_status ss_injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, double tol, int mmax,
+                            ss_c128 *inj, int *rank) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || s < 1 || mmax < 1) return fail(ctx, SS_ERR_ARG, "ss_injection_left: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_injection_left: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!sigma || !inj) return fail(ctx, SS_ERR_ARG, "ss_injection_left: null pointer");
+  return injection_left(ctx, batch, s, sigma, tol, mmax, inj, rank);
+}
+
+ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, const ss_c128 *Q,
+                        const ss_c128 *sigma, int m, const ss_c128 *inj, ss_c128 *psi, double tol, int max_iter,
+                        int *iters, double *resid) {
+  SS_TRY(enter(ctx));
+  if (!hs || batch < 0 || m < 1 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
+    return fail(ctx, SS_ERR_ARG, "ss_refine_psi: size out of range");
+  if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_refine_psi: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!hs->H_diag || !hs->S_diag || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)) || !E || !Q || !sigma ||
+      !inj || !psi)
+    return fail(ctx, SS_ERR_ARG, "ss_refine_psi: null pointer");
+  return refine_psi(ctx, hs, batch, kidx, E, Q, sigma, m, inj, psi, tol, max_iter, iters, resid);
+}
+
+ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
+                              double *T) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || nb < 1 || s < 1 || m < 1) return fail(ctx, SS_ERR_ARG, "ss_transmission_psi: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_transmission_psi: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!psi || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission_psi: null pointer");
+  return transmission_psi(ctx, batch, nb, s, m, psi, sigma, T);
 }
 
 }  // extern "C"

@@ -60,6 +60,9 @@ enum Slot {
   kSlotDec,        // decimation state
   kSlotObc,        // corner system work
   kSlotMisc,
+  kSlotFact,       // kept factorizations of the first-column recursion (for refinement)
+  kSlotFactPerm,
+  kSlotRef,        // refinement work
   kNumSlots
 };
 
@@ -71,6 +74,12 @@ struct ss_ctx {
   std::string err;
   ss::Buffer slot[ss::kNumSlots];
   int *host_word = nullptr;  // pinned word for convergence polls
+  bool sync_free = false;    // never wait for the stream inside a call (stream/graph capture)
+  // what the kept workspaces currently describe (for ss_refine_psi)
+  bool fact_valid = false;   // kSlotX + kSlotFact/FactPerm hold a first-column recursion
+  int fact_batch = 0, fact_nb = 0, fact_s = 0;
+  bool corner_valid = false;  // kSlotM/kSlotPerm hold the factored corner systems of ss_apply_obc
+  int corner_batch = 0, corner_s = 0, corner_ldm = 0;
   // kernel timing probe: launches of `timer_family` are bracketed by event pairs
   std::string timer_family;
   std::vector<hipEvent_t> timer_events;

@@ -5,8 +5,8 @@
 
 namespace ss {
 
-ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
-                             ss_c128 *Q, int *info);
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
+                             int flags, ss_c128 *Q, int *info);
 
 ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
                           const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
@@ -17,5 +17,15 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
                     const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info);
 
 ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T);
+
+ss_status injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, double tol, int mmax, ss_c128 *inj,
+                         int *rank);
+
+ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, const ss_c128 *Q,
+                     const ss_c128 *sigma, int m, const ss_c128 *inj, ss_c128 *psi, double tol, int max_iter,
+                     int *iters, double *resid);
+
+ss_status transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
+                           double *T);
 
 }  // namespace ss

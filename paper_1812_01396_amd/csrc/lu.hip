@@ -35,7 +35,21 @@ struct LuArgs {
   int n, nrhs;
   const int *skip;
   int skip_shift;
+  double2 *B;  // right-hand sides (columns >= n) when non-null
+  long sB;
+  int ldb;
 };
+
+// Base pointer and leading dimension for columns starting at c of system mat: columns >= n live in the
+// separate right-hand-side buffer when one is given (a column range never straddles n).
+struct ColView {
+  double2 *p;
+  long ld;
+};
+__device__ __forceinline__ ColView col_view(const LuArgs &a, int mat, int c) {
+  if (a.B != nullptr && c >= a.n) return ColView{a.B + (long)mat * a.sB - a.n, a.ldb};
+  return ColView{a.M + (long)mat * a.sM, a.ldm};
+}
 
 __device__ __forceinline__ bool skipped(const LuArgs &a, int mat) {
   return a.skip != nullptr && a.skip[mat >> a.skip_shift] != 0;
@@ -46,6 +60,7 @@ static LuArgs make_args(const LuDesc &d) {
   a.M = d.M; a.sM = d.sM; a.ldm = d.ldm; a.perm = d.perm; a.sP = d.sP;
   a.zp = d.zp; a.X = d.X; a.sX = d.sX; a.ldx = d.ldx; a.n = d.n; a.nrhs = d.nrhs;
   a.skip = d.skip; a.skip_shift = d.skip_shift;
+  a.B = d.B; a.sB = d.sB; a.ldb = d.ldb;
   return a;
 }
 
@@ -230,18 +245,19 @@ __global__ void __launch_bounds__(LuTile::NT) k_lu_gemm(LuArgs a, int r_lo, int 
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
+  const ColView cv = col_view(a, mat, c_lo);
   load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
   const int tc = cdiv(c_hi - c_lo, T::BN);
   const int m0 = r_lo + (blockIdx.x / tc) * T::BM, n0 = c_lo + (blockIdx.x % tc) * T::BN;
   Acc<T> acc;
   acc.zero();
   LdRowPerm la{M, a.ldm, sperm};
-  LdRowPerm lb{M, a.ldm, sperm};
+  LdRowPerm lb{cv.p, cv.ld, sperm};
   mma_loop<T>(la, lb, m0, r_hi, n0, c_hi, k_lo, k_hi, acc, lds);
   acc_foreach<T>(acc, [&](int r, int c, double2 val) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < r_hi && gc < c_hi) {
-      double2 *p = M + (long)sperm[gr] * a.ldm + gc;
+      double2 *p = cv.p + (long)sperm[gr] * cv.ld + gc;
       *p = csub(*p, val);
     }
   });
@@ -307,6 +323,7 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, i
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
+  const ColView cv = col_view(a, mat, c_lo);
   const int *perm = a.perm + (long)mat * a.sP;
   const int w = min(W, a.n - r0);
   const int c0 = c_lo + blockIdx.x * 64;
@@ -314,7 +331,7 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, i
   __syncthreads();
   for (int idx = threadIdx.x; idx < W * 64; idx += 256) {
     const int i = idx / 64, c = idx % 64;
-    const double2 v = (i < w && c0 + c < c_hi) ? M[(long)sp[i] * a.ldm + c0 + c] : make_double2(0.0, 0.0);
+    const double2 v = (i < w && c0 + c < c_hi) ? cv.p[(long)sp[i] * cv.ld + c0 + c] : make_double2(0.0, 0.0);
     cr[i * CP + c] = v.x;
     ci[i * CP + c] = v.y;
   }
@@ -324,7 +341,7 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, i
   }
   __syncthreads();
   tile_trsm<W, CP, kUpper>(cr, ci, tri, w, [&](int i, int col, double2 v) {
-    if (c0 + col < c_hi) M[(long)sp[i] * a.ldm + c0 + col] = v;
+    if (c0 + col < c_hi) cv.p[(long)sp[i] * cv.ld + c0 + col] = v;
   });
 }
 
@@ -332,13 +349,13 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, i
 __global__ void k_copy_out(LuArgs a) {
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
-  const double2 *M = a.M + (long)mat * a.sM;
+  const ColView cv = col_view(a, mat, a.n);
   const int *perm = a.perm + (long)mat * a.sP;
   double2 *X = a.X + (long)mat * a.sX;
   const long total = (long)a.n * a.nrhs;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     const int r = idx / a.nrhs, c = idx % a.nrhs;
-    X[(long)r * a.ldx + c] = M[(long)perm[r] * a.ldm + a.n + c];
+    X[(long)r * a.ldx + c] = cv.p[(long)perm[r] * cv.ld + a.n + c];
   }
 }
 
@@ -397,8 +414,8 @@ struct LuRun {
     gemm(cm, d.n, cm, c1, c0, cm);
     factor(cm, c1);
   }
-  ss_status run() {
-    factor(0, d.n);
+  ss_status run(bool do_factor = true) {
+    if (do_factor) factor(0, d.n);
     if (d.nrhs > 0) {
       trsm_lower(0, d.n, d.n, d.n + d.nrhs);
       trsm_upper(0, d.n, d.n, d.n + d.nrhs);
@@ -417,6 +434,15 @@ ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run();
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run();
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run();
+}
+
+ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
+  if (d.nmat <= 0) return SS_OK;
+  if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_apply: order out of range");
+  const int W = lu_panel_width(d.n);
+  if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run(false);
+  if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run(false);
+  return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run(false);
 }
 
 ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d) {

@@ -24,6 +24,11 @@ struct LuDesc {
   // optional: system i is skipped (every kernel returns at once) when skip[i >> skip_shift] != 0
   const int *skip = nullptr;
   int skip_shift = 0;
+  // optional: right-hand sides in a separate buffer (rows in physical order, ld ldb) instead of
+  // columns [n, n + nrhs) of M
+  double2 *B = nullptr;
+  long sB = 0;
+  int ldb = 0;
 };
 
 // Panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to 2048).
@@ -35,5 +40,8 @@ constexpr int kLuMaxN = 2048;
 // augmented matrices and sets perm to the identity (or lets `lu_identity_perm` do it).
 ss_status lu_solve(ss_ctx *ctx, const LuDesc &d);
 ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d);
+// Apply factors kept from an earlier lu_solve (M holds L\U in physical rows, perm the row map) to new
+// right-hand sides: X = U^{-1} L^{-1} P RHS (no factorization).
+ss_status lu_apply(ss_ctx *ctx, const LuDesc &d);
 
 }  // namespace ss

@@ -380,8 +380,9 @@ ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *
       hipLaunchKernelGGL(k_dec_update, dim3(tiles * tiles, batch), dim3(DecTile::NT), 0, ctx->stream, a, it & 1);
     }
     hipLaunchKernelGGL(k_dec_check, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a, it);
-    // every few passes, stop early once every instance has converged
-    if (it >= 3 && (it % 4 == 3)) {
+    // every few passes, stop early once every instance has converged (unless the context must not
+    // wait for its stream: then all max_iter passes are enqueued and converged instances skip them)
+    if (!ctx->sync_free && it >= 3 && (it % 4 == 3)) {
       if (hipMemcpyAsync(hostDone, a.ndone, sizeof(int), hipMemcpyDeviceToHost, ctx->stream) != hipSuccess ||
           hipStreamSynchronize(ctx->stream) != hipSuccess) {
         st = fail(ctx, SS_ERR_DEVICE, "lead_selfenergy: convergence poll");

@@ -16,6 +16,7 @@
 #include "lu.hpp"
 #include "drivers.hpp"
 #include "tile.hpp"
+#include "tile32.hpp"
 
 namespace ss {
 
@@ -43,8 +44,29 @@ __device__ __forceinline__ int set_of(const SweepArgs &a, int inst) {
 }
 
 using FormTile = TileCfg<64, 64, 16, 2, 2>;
+using FormTile32 = TileCfg32<64, 64, 32, 2, 2>;
+static_assert(FormTile32::LDS_FLOATS <= 2 * FormTile::LDS_DOUBLES, "shared staging buffer too small");
+
+// acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in FP64 (kF32 == false) or with FP32 operands
+// and FP32 accumulation (kF32 == true); f(r, c, value) receives every element of the tile.
+template <bool kF32, class LA, class LB, class F>
+__device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0, int M, int n0, int N, int kbeg,
+                                             int kend, double *lds, F &&f) {
+  if constexpr (kF32) {
+    Acc32<FormTile32> acc;
+    acc.zero();
+    mma_loop32<FormTile32>(la, lb, m0, M, n0, N, kbeg, kend, acc, reinterpret_cast<float *>(lds));
+    acc_foreach32<FormTile32>(acc, f);
+  } else {
+    Acc<FormTile> acc;
+    acc.zero();
+    mma_loop<FormTile>(la, lb, m0, M, n0, N, kbeg, kend, acc, lds);
+    acc_foreach<FormTile>(acc, f);
+  }
+}
 
 // Forms [D | RHS] of step t for every system; fold the previous step's zero pivot into `code`.
+template <bool kF32>
 __global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
@@ -72,29 +94,29 @@ __global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
   if (tile < ntile) {
     // D tile: D = A_ib,ib - coupling * previous solution
     const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
-    Acc<T> acc;
-    acc.zero();
-    const bool has_prev = t > 0;
-    if (has_prev) {
-      const double2 *xp = a.X + ((long)mat * nb + (t - 1)) * ss2;
-      LdRow lb{xp, s};
-      if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
-        LdForm<false> la{a.Hu + ks * a.kstride_u + ib * ss2, a.Su + ks * a.kstride_u + ib * ss2, s, e};
-        mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
-      } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
-        LdForm<true> la{a.Hu + ks * a.kstride_u + (ib - 1) * ss2, a.Su + ks * a.kstride_u + (ib - 1) * ss2,
-                        s, e};
-        mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
-      }
-    }
-    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+    auto store = [&](int r, int c, double2 v) {
       const int gr = m0 + r, gc = n0 + c;
       if (gr < s && gc < s) {
         const long o = (long)gr * s + gc;
         const double2 av = make_double2(e * sd[o].x - hd[o].x, e * sd[o].y - hd[o].y);
         M[(long)gr * 2 * s + gc] = csub(av, v);
       }
-    });
+    };
+    if (t > 0) {
+      const double2 *xp = a.X + ((long)mat * nb + (t - 1)) * ss2;
+      LdRow lb{xp, s};
+      if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
+        LdForm<false> la{a.Hu + ks * a.kstride_u + ib * ss2, a.Su + ks * a.kstride_u + ib * ss2, s, e};
+        tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
+      } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
+        LdForm<true> la{a.Hu + ks * a.kstride_u + (ib - 1) * ss2, a.Su + ks * a.kstride_u + (ib - 1) * ss2,
+                        s, e};
+        tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
+      }
+    } else {
+      for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT)
+        store(idx / T::BN, idx % T::BN, make_double2(0.0, 0.0));
+    }
     if (n0 == 0) {
       for (int r = threadIdx.x; r < T::BM; r += T::NT)
         if (m0 + r < s) a.perm[(long)mat * s + m0 + r] = m0 + r;
@@ -146,6 +168,7 @@ __global__ void k_code_init(int *code, int n) {
 }
 
 // Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
+template <bool kF32>
 __global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
@@ -166,19 +189,31 @@ __global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
   }
   const int pb = dir == 0 ? ib - 1 : ib + 1;
   const double2 *qp = a.Q + (long)inst * nb * 2 * ss2 + (long)pb * 2 * ss2 + (dir ? s : 0);
-  Acc<T> acc;
-  acc.zero();
   LdRow la{x, s};
   LdRow lb{qp, 2 * s};
-  mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
-  acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+  tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < s && gc < s) qi[(long)gr * 2 * s + gc] = cneg(v);
   });
 }
 
-ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
-                             ss_c128 *Q, int *info) {
+// Keep the factorization of the first-column recursion's step t (L\U in physical rows and the row
+// map) for later solves with the same diagonal systems.
+__global__ void k_save_factors(SweepArgs a, double2 *F, int *P, int t) {
+  const int inst = blockIdx.y, s = a.s;
+  const long ss2 = (long)s * s;
+  const double2 *M = a.M + (long)(2 * inst) * 2 * ss2;
+  double2 *f = F + ((long)inst * a.nb + t) * ss2;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < ss2; idx += (long)gridDim.x * blockDim.x) {
+    const int r = idx / s, c = idx % s;
+    f[idx] = M[(long)r * 2 * s + c];
+  }
+  if (blockIdx.x == 0)
+    for (int r = threadIdx.x; r < s; r += blockDim.x) P[((long)inst * a.nb + t) * s + r] = a.perm[(long)(2 * inst) * s + r];
+}
+
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
+                             int flags, ss_c128 *Q, int *info) {
   const int s = hs->s, nb = hs->nb, nmat = 2 * batch;
   const long ss2 = (long)s * s;
   const int n = s, nrhs = s, ldm = 2 * s;
@@ -223,22 +258,45 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   d.sX = (long)nb * ss2;
   d.ldx = s;
 
+  double2 *F = nullptr;
+  int *P = nullptr;
+  const bool keep = (flags & SS_KEEP_FACTORS) != 0;
+  if (keep) {
+    SS_TRY(workspace(ctx, kSlotFact, sizeof(double2) * (size_t)batch * nb * ss2, (void **)&F));
+    SS_TRY(workspace(ctx, kSlotFactPerm, sizeof(int) * (size_t)batch * nb * s, (void **)&P));
+  }
+  ctx->fact_valid = false;
+  const bool f32 = prec == SS_PREC_FP32;
   hipLaunchKernelGGL(k_code_init, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a.code, batch);
   const int tiles = cdiv(s, FormTile::BM);
   for (int t = 0; t < nb; ++t) {
     {
       KernelScope ks_(ctx, "form");
-      hipLaunchKernelGGL(k_form, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
+      if (f32)
+        hipLaunchKernelGGL(k_form<true>, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
+      else
+        hipLaunchKernelGGL(k_form<false>, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
     }
     d.X = a.X + (long)t * ss2;
     SS_TRY(lu_solve(ctx, d));
+    if (keep)
+      hipLaunchKernelGGL(k_save_factors, dim3(std::min(cdiv((int)std::min<long>(ss2, 1 << 30), 256), 64), batch),
+                         dim3(256), 0, ctx->stream, a, F, P, t);
   }
   hipLaunchKernelGGL(k_sweep_finish, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a);
-  for (int u = 0; u < nb; ++u)
-    {
-      KernelScope ks_(ctx, "chain");
-      hipLaunchKernelGGL(k_chain, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
-    }
+  for (int u = 0; u < nb; ++u) {
+    KernelScope ks_(ctx, "chain");
+    if (f32)
+      hipLaunchKernelGGL(k_chain<true>, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
+    else
+      hipLaunchKernelGGL(k_chain<false>, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
+  }
+  if (keep) {
+    ctx->fact_valid = true;
+    ctx->fact_batch = batch;
+    ctx->fact_nb = nb;
+    ctx->fact_s = s;
+  }
   return check_launch(ctx, "precompute_columns");
 }
 

@@ -17,10 +17,14 @@ LIB_PATH = os.path.join(_HERE, "libsplitsolve.so")
 
 SS_OK, SS_ERR_ARG, SS_ERR_NOMEM, SS_ERR_DEVICE, SS_ERR_UNSUPPORTED = range(5)
 SS_MAX_S = 1024
+SS_PREC_FP64, SS_PREC_FP32 = 0, 1
+SS_KEEP_FACTORS = 1
 
 EXPORTS = (
-    "ss_create", "ss_destroy", "ss_set_stream", "ss_synchronize", "ss_status_string", "ss_last_error",
-    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy", "ss_precompute_columns", "ss_apply_obc", "ss_transmission",
+    "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_synchronize", "ss_status_string", "ss_last_error",
+    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy",
+    "ss_precompute_columns", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
+    "ss_transmission_psi",
 )
 
 
@@ -57,6 +61,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_destroy.restype = None
     lib.ss_set_stream.argtypes = [P, P]
     lib.ss_set_stream.restype = I
+    lib.ss_set_sync_free.argtypes = [P, I]
+    lib.ss_set_sync_free.restype = I
     lib.ss_synchronize.argtypes = [P]
     lib.ss_synchronize.restype = I
     lib.ss_status_string.argtypes = [I]
@@ -71,12 +77,18 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_kernel_timer_read.restype = I
     lib.ss_lead_selfenergy.argtypes = [P, I, I, I, P, P, P, P, P, P, D, D, I, P, P, P, P]
     lib.ss_lead_selfenergy.restype = I
-    lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, P, P]
+    lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, I, I, P, P]
     lib.ss_precompute_columns.restype = I
     lib.ss_apply_obc.argtypes = [P, I, I, I, P, P, I, P, P, P, P]
     lib.ss_apply_obc.restype = I
     lib.ss_transmission.argtypes = [P, I, I, P, P, P]
     lib.ss_transmission.restype = I
+    lib.ss_injection_left.argtypes = [P, I, I, P, D, I, P, P]
+    lib.ss_injection_left.restype = I
+    lib.ss_refine_psi.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, P, P, I, P, P, D, I, P, P]
+    lib.ss_refine_psi.restype = I
+    lib.ss_transmission_psi.argtypes = [P, I, I, I, I, P, P, P]
+    lib.ss_transmission_psi.restype = I
     _lib = lib
     return lib
 
@@ -135,6 +147,10 @@ class Context:
             msg = self.lib.ss_last_error(self.handle).decode()
             raise SplitSolveError(st, f"{self.lib.ss_status_string(st).decode()}: {msg}")
 
+    def set_sync_free(self, on: bool):
+        """Never wait for the stream inside a call (for stream/graph capture)."""
+        self.check(self.lib.ss_set_sync_free(self.handle, int(bool(on))))
+
     def synchronize(self):
         self.check(self.lib.ss_synchronize(self.handle))
 
@@ -182,13 +198,7 @@ def ss_lead_selfenergy(ctx: Context, H00, H01, S00, S01, E, eta: float, tol: flo
     return sigma, iters, resid, info
 
 
-def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, info=None, validate: bool = True):
-    """Q = first and last block columns of (E S - H)^{-1} for every instance (Sec. 3B, Step 1).
-
-    Hd, Sd: [nk, nb, s, s]; Hu, Su: [nk, nb-1, s, s] (or without the leading nk).  E: [batch] float64.
-    Returns (Q [batch, nb, s, 2s], info [batch] int32).
-    """
-    dev = ctx.device
+def _btd(Hd, Hu, Sd, Su, dev):
     if Hd.dim() == 3:
         Hd, Hu, Sd, Su = (x.unsqueeze(0) for x in (Hd, Hu, Sd, Su))
     nk, nb, s, _ = Hd.shape
@@ -196,6 +206,21 @@ def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, in
     _need(Sd, torch.complex128, dev, "Sd", (nk, nb, s, s))
     _need(Hu, torch.complex128, dev, "Hu", (nk, nb - 1, s, s))
     _need(Su, torch.complex128, dev, "Su", (nk, nb - 1, s, s))
+    btd = _Btd(nb, s, nk, Hd.data_ptr(), Hu.data_ptr() if nb > 1 else 0, Sd.data_ptr(),
+               Su.data_ptr() if nb > 1 else 0)
+    return btd, nk, nb, s
+
+
+def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, info=None, validate: bool = True,
+                          prec: int = SS_PREC_FP64, keep_factors: bool = False):
+    """Q = first and last block columns of (E S - H)^{-1} for every instance (Sec. 3B, Step 1).
+
+    Hd, Sd: [nk, nb, s, s]; Hu, Su: [nk, nb-1, s, s] (or without the leading nk).  E: [batch] float64.
+    prec: SS_PREC_FP64 or SS_PREC_FP32 (products of the recursion); keep_factors keeps the first-column
+    recursion's factors in the context for ss_refine_psi.  Returns (Q [batch, nb, s, 2s], info [batch]).
+    """
+    dev = ctx.device
+    btd, nk, nb, s = _btd(Hd, Hu, Sd, Su, dev)
     _need(E, torch.float64, dev, "E")
     batch = E.numel()
     if kidx is not None:
@@ -205,10 +230,9 @@ def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, in
     Q = Q if Q is not None else torch.empty(batch, nb, s, 2 * s, dtype=torch.complex128, device=dev)
     info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
     _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
-    btd = _Btd(nb, s, nk, Hd.data_ptr(), Hu.data_ptr() if nb > 1 else 0, Sd.data_ptr(),
-               Su.data_ptr() if nb > 1 else 0)
-    ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), _ptr(Q),
-                                            _ptr(info)))
+    flags = SS_KEEP_FACTORS if keep_factors else 0
+    ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), int(prec),
+                                            flags, _ptr(Q), _ptr(info)))
     return Q, info
 
 
@@ -247,4 +271,51 @@ def ss_transmission(ctx: Context, gc, sigma, T=None):
     T = T if T is not None else torch.empty(batch, 2, dtype=torch.float64, device=dev)
     _need(T, torch.float64, dev, "T", (batch, 2))
     ctx.check(ctx.lib.ss_transmission(ctx.handle, batch, s, _ptr(gc), _ptr(sigma), _ptr(T)))
+    return T
+
+
+def ss_injection_left(ctx: Context, sigma, mmax: int, tol: float = 0.0, inj=None, rank=None):
+    """b' = [W_L; 0] with W_L W_L^H ~ Gamma_L (pivoted Cholesky).  Returns (inj [batch, 2s, mmax], rank [batch])."""
+    dev = ctx.device
+    batch, _, s, _ = sigma.shape
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    inj = inj if inj is not None else torch.empty(batch, 2 * s, mmax, dtype=torch.complex128, device=dev)
+    rank = rank if rank is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    _need(inj, torch.complex128, dev, "inj", (batch, 2 * s, mmax))
+    ctx.check(ctx.lib.ss_injection_left(ctx.handle, batch, s, _ptr(sigma), float(tol), int(mmax), _ptr(inj),
+                                        _ptr(rank)))
+    return inj, rank
+
+
+def ss_refine_psi(ctx: Context, Hd, Hu, Sd, Su, E, Q, sigma, inj, psi, kidx=None, tol: float = 0.0,
+                  max_iter: int = 0, iters=None, resid=None):
+    """Refine psi in place on the full system (kept factors of the last precompute with keep_factors and
+    the corner factorization of the last ss_apply_obc on this context).  Returns (psi, iters, resid)."""
+    dev = ctx.device
+    btd, nk, nb, s = _btd(Hd, Hu, Sd, Su, dev)
+    batch = E.numel()
+    m = inj.shape[-1]
+    _need(E, torch.float64, dev, "E")
+    _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    _need(inj, torch.complex128, dev, "inj", (batch, 2 * s, m))
+    _need(psi, torch.complex128, dev, "psi", (batch, nb, s, m))
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+    iters = iters if iters is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    resid = resid if resid is not None else torch.empty(batch, dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.ss_refine_psi(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), _ptr(Q),
+                                    _ptr(sigma), m, _ptr(inj), _ptr(psi), float(tol), int(max_iter), _ptr(iters),
+                                    _ptr(resid)))
+    return psi, iters, resid
+
+
+def ss_transmission_psi(ctx: Context, psi, sigma, T=None):
+    """T = Re Tr[psi_nb^H Gamma_R psi_nb] for psi injected from the left.  Returns T [batch] float64."""
+    dev = ctx.device
+    batch, nb, s, m = psi.shape
+    _need(psi, torch.complex128, dev, "psi")
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    T = T if T is not None else torch.empty(batch, dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.ss_transmission_psi(ctx.handle, batch, nb, s, m, _ptr(psi), _ptr(sigma), _ptr(T)))
     return T
