@@ -195,6 +195,59 @@ ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kid
 ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi,
                               const ss_c128 *sigma, double *T);
 
+/* ---------------------------------------------------------------- uneven batches
+ * Many independent (E, k) instances of different block size s and block count nb (the paper solves
+ * energy points independently side by side, Sec. 4).  A plan groups the instances by s, sorts each
+ * group by nb and splits it into chunks that fit `mem_bytes`; a chunk runs the whole hot path
+ * (self-energies, Step 1, Steps 2-4, Caroli T) in lockstep, launching at recursion step t only the
+ * instances with more than t blocks.  Groups run on streams of their own.  With use_graph the whole
+ * batch is captured once into one graph at creation and every ss_plan_execute is one graph launch.
+ * With autotune, candidate LU panel widths and chunk sizes are timed per group at creation.
+ *
+ * Instance blocks are device pointers owned by the caller and must stay valid and unmoved for the
+ * plan's life (the plan and its graph keep the addresses; the values are read at every execution).
+ * The lead of both sides is the semi-infinite repetition of (H00, H01, S00, S01) as in
+ * ss_lead_selfenergy.  psi (optional) receives [nb][s][m] for the injection b' = [W_L; 0] of
+ * ss_injection_left with at most m columns (unused columns are zero). */
+typedef struct {
+  int nb, s;
+  double E;
+  const ss_c128 *H_diag, *H_upper, *S_diag, *S_upper; /* [nb][s][s], [nb-1][s][s] */
+  const ss_c128 *H00, *H01, *S00, *S01;               /* [s][s] each */
+  ss_c128 *psi;                                       /* [nb][s][m] or NULL */
+} ss_instance;
+
+typedef struct {
+  double eta;        /* broadening of the lead's diagonal cell (>= 0) */
+  double sigma_tol;  /* decimation tolerance (0: 1e-14) */
+  int sigma_passes;  /* decimation passes enqueued (0: 64); converged instances skip later passes */
+  int m;             /* columns of psi (0: psi is not formed; then every instance's psi must be NULL) */
+  int use_graph;     /* nonzero: capture the batch into one graph at creation */
+  int autotune;      /* nonzero: time candidate panel widths and chunk sizes per group at creation */
+  size_t mem_bytes;  /* device memory for chunk work (0: 32 GiB); a chunk always holds one instance */
+} ss_plan_opts;
+
+typedef struct ss_plan ss_plan;
+
+/* Build a plan for n instances (host array, copied).  T [n][2] (T_LR, T_RL) and info [n][3]
+ * (self-energy, Step 1 and corner codes as in the single calls) are device outputs in the caller's
+ * order, written by every execution.  Creation runs the batch once (the outputs then already hold a
+ * result) and waits for it.  The plan runs on ctx's device and is ordered with ctx's stream. */
+ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_plan_opts *opts, double *T,
+                         int *info, ss_plan **plan);
+/* Enqueue one execution of the whole batch after the work already on ctx's stream; later work on
+ * that stream waits for it. */
+ss_status ss_plan_execute(ss_plan *plan);
+/* Groups of the plan (by block size) and, per group: s, instance count, chunk size, LU panel width,
+ * and the autotuner's best probe time in ms (0 without autotune). */
+int ss_plan_groups(const ss_plan *plan);
+ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, int *chunk, int *lu_width,
+                           double *tune_ms);
+/* Nodes of the captured graph (0 without use_graph). */
+long long ss_plan_graph_nodes(const ss_plan *plan);
+/* Waits for the plan's work and frees it. */
+void ss_plan_destroy(ss_plan *plan);
+
 #ifdef __cplusplus
 }
 #endif

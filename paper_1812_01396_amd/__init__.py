@@ -7,6 +7,8 @@ Caroli transmission.  See include/splitsolve.h for the ABI.
 """
 from .splitsolve import (  # noqa: F401
     Context,
+    Instance,
+    Plan,
     SplitSolveError,
     load_library,
     SS_PREC_FP32,

@@ -75,6 +75,7 @@ struct ss_ctx {
   ss::Buffer slot[ss::kNumSlots];
   int *host_word = nullptr;  // pinned word for convergence polls
   bool sync_free = false;    // never wait for the stream inside a call (stream/graph capture)
+  int lu_width = 0;          // LU panel width to use where valid for the order (0: the default)
   // what the kept workspaces currently describe (for ss_refine_psi)
   bool fact_valid = false;   // kSlotX + kSlotFact/FactPerm hold a first-column recursion
   int fact_batch = 0, fact_nb = 0, fact_s = 0;

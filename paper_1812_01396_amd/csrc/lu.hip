@@ -22,6 +22,15 @@ namespace ss {
 
 int lu_panel_width(int n) { return n <= 512 ? 32 : (n <= 1024 ? 16 : 8); }
 
+bool lu_panel_width_ok(int n, int w) {
+  // a panel keeps R rows per thread in one workgroup: W 32 (R 1, 512 threads), 16 (R 1, 1024), 8 (R 2, 1024)
+  return (w == 32 && n <= 512) || (w == 16 && n <= 1024) || (w == 8 && n <= 2048);
+}
+
+static int panel_width(const ss_ctx *ctx, int n) {
+  return lu_panel_width_ok(n, ctx->lu_width) ? ctx->lu_width : lu_panel_width(n);
+}
+
 struct LuArgs {
   double2 *M;
   long sM;
@@ -31,6 +40,7 @@ struct LuArgs {
   int *zp;
   double2 *X;
   long sX;
+  const long *xoff;
   int ldx;
   int n, nrhs;
   const int *skip;
@@ -58,7 +68,7 @@ __device__ __forceinline__ bool skipped(const LuArgs &a, int mat) {
 static LuArgs make_args(const LuDesc &d) {
   LuArgs a;
   a.M = d.M; a.sM = d.sM; a.ldm = d.ldm; a.perm = d.perm; a.sP = d.sP;
-  a.zp = d.zp; a.X = d.X; a.sX = d.sX; a.ldx = d.ldx; a.n = d.n; a.nrhs = d.nrhs;
+  a.zp = d.zp; a.X = d.X; a.sX = d.sX; a.xoff = d.xoff; a.ldx = d.ldx; a.n = d.n; a.nrhs = d.nrhs;
   a.skip = d.skip; a.skip_shift = d.skip_shift;
   a.B = d.B; a.sB = d.sB; a.ldb = d.ldb;
   return a;
@@ -351,7 +361,7 @@ __global__ void k_copy_out(LuArgs a) {
   if (skipped(a, mat)) return;
   const ColView cv = col_view(a, mat, a.n);
   const int *perm = a.perm + (long)mat * a.sP;
-  double2 *X = a.X + (long)mat * a.sX;
+  double2 *X = a.X + (a.xoff ? a.xoff[mat] : (long)mat * a.sX);
   const long total = (long)a.n * a.nrhs;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
     const int r = idx / a.nrhs, c = idx % a.nrhs;
@@ -430,7 +440,7 @@ struct LuRun {
 ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_solve: order out of range");
-  const int W = lu_panel_width(d.n);
+  const int W = panel_width(ctx, d.n);
   if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run();
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run();
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run();
@@ -439,7 +449,7 @@ ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
 ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_apply: order out of range");
-  const int W = lu_panel_width(d.n);
+  const int W = panel_width(ctx, d.n);
   if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run(false);
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run(false);
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run(false);

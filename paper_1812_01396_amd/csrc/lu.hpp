@@ -20,6 +20,7 @@ struct LuDesc {
   int *zp = nullptr;  // [nmat]: 1 + first column with an exactly zero pivot, 0 if none
   double2 *X = nullptr;
   long sX = 0;
+  const long *xoff = nullptr;  // optional per-system offsets of X (elements) in place of mat * sX
   int ldx = 0;
   // optional: system i is skipped (every kernel returns at once) when skip[i >> skip_shift] != 0
   const int *skip = nullptr;
@@ -31,8 +32,10 @@ struct LuDesc {
   int ldb = 0;
 };
 
-// Panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to 2048).
+// Default panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to
+// 2048); a context may ask for another width (ss_ctx::lu_width) where lu_panel_width_ok allows it.
 int lu_panel_width(int n);
+bool lu_panel_width_ok(int n, int w);
 // Largest order supported.
 constexpr int kLuMaxN = 2048;
 

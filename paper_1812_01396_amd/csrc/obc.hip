@@ -55,16 +55,24 @@ struct ObcArgs {
   const double2 *Q, *sigma, *inj;
   double2 *psi, *gc;
   int nb, s, m, batch;
+  const int *nbv;               // per-instance block counts (null: nb)
+  const long *boff;             // first block of each instance in the packed Q (null: inst * nb)
+  double2 *const *psi_tab;      // per-instance psi destinations (null: psi packed like Q)
   double2 *M;   // [batch][2s][4s+m]
   double2 *CQ;  // [batch][2s][2s]
   double2 *X;   // [batch][2s][2s+m]
 };
 
 // C Q, R = I - C Q and the identity block: grid (2 halves * tiles(s) * tiles(2s), batch)
+__device__ __forceinline__ int obc_nb(const ObcArgs &a, int inst) { return a.nbv ? a.nbv[inst] : a.nb; }
+__device__ __forceinline__ const double2 *obc_q(const ObcArgs &a, int inst) {
+  return a.Q + (a.boff ? a.boff[inst] : (long)inst * a.nb) * 2 * (long)a.s * a.s;
+}
+
 __global__ void __launch_bounds__(ObcTile::NT) k_obc_cq(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int inst = blockIdx.y, s = a.s, nb = a.nb;
+  const int inst = blockIdx.y, s = a.s, nb = obc_nb(a, inst);
   const int tr = cdiv(s, T::BM), tc = cdiv(2 * s, T::BN);
   int t = blockIdx.x;
   const int half = t / (tr * tc);
@@ -72,7 +80,7 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_cq(ObcArgs a) {
   const int m0 = (t / tc) * T::BM, n0 = (t % tc) * T::BN;
   const long ss2 = (long)s * s;
   const double2 *sig = a.sigma + ((long)inst * 2 + half) * ss2;  // half 0: Sigma_L, 1: Sigma_R
-  const double2 *qrow = a.Q + (long)inst * nb * 2 * ss2 + (half ? (long)(nb - 1) * 2 * ss2 : 0);
+  const double2 *qrow = obc_q(a, inst) + (half ? (long)(nb - 1) * 2 * ss2 : 0);
   Acc<T> acc;
   acc.zero();
   LdRow la{sig, s};
@@ -123,7 +131,7 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_gc(ObcArgs a) {
   const int ldx = 2 * s + a.m;
   Acc<T> acc;
   acc.zero();
-  LdCorner la{a.Q + (long)inst * a.nb * 2 * s * s, s, a.nb};
+  LdCorner la{obc_q(a, inst), s, obc_nb(a, inst)};
   LdRow lb{a.X + (long)inst * 2 * s * ldx, ldx};
   mma_loop<T>(la, lb, m0, 2 * s, n0, 2 * s, 0, 2 * s, acc, lds);
   double2 *g = a.gc + (long)inst * 4 * s * s;
@@ -138,16 +146,19 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_psi(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;
-  const int rows = a.nb * s;
+  const int rows = obc_nb(a, inst) * s;
   const int tc = cdiv(m, T::BN);
   const int m0 = (blockIdx.x / tc) * T::BM, n0 = (blockIdx.x % tc) * T::BN;
+  if (m0 >= rows) return;  // the grid covers the largest instance
+  double2 *p = a.psi_tab ? a.psi_tab[inst]
+                         : a.psi + (a.boff ? a.boff[inst] : (long)inst * a.nb) * (long)s * m;
+  if (p == nullptr) return;
   const int ldx = 2 * s + m;
   Acc<T> acc;
   acc.zero();
-  LdRow la{a.Q + (long)inst * rows * 2 * s, 2 * s};
+  LdRow la{obc_q(a, inst), 2 * s};
   LdSum lb{a.inj + (long)inst * 2 * s * m, a.X + (long)inst * 2 * s * ldx + 2 * s, m, ldx};
   mma_loop<T>(la, lb, m0, rows, n0, m, 0, 2 * s, acc, lds);
-  double2 *p = a.psi + (long)inst * rows * m;
   acc_foreach<T>(acc, [&](int r, int c, double2 v) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < rows && gc < m) p[(long)gr * m + gc] = v;
@@ -159,8 +170,8 @@ __global__ void k_obc_info(const int *zp, int *info, int batch) {
   if (i < batch && info) info[i] = zp[i];
 }
 
-ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+static ss_status obc_run(ss_ctx *ctx, ObcArgs &a, int nb_max, bool want_psi, int *info) {
+  const int batch = a.batch, s = a.s, m = a.m;
   const long ss2 = (long)s * s;
   const int n = 2 * s, nrhs = 2 * s + m, ldm = 4 * s + m;
   void *wM, *wP, *wZ, *wO;
@@ -168,16 +179,6 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
   SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * (size_t)batch * n, &wP));
   SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)batch, &wZ));
   SS_TRY(workspace(ctx, kSlotObc, sizeof(double2) * (size_t)batch * (4 * ss2 + (long)n * nrhs), &wO));
-  ObcArgs a;
-  a.Q = (const double2 *)Q;
-  a.sigma = (const double2 *)sigma;
-  a.inj = (const double2 *)inj;
-  a.psi = (double2 *)psi;
-  a.gc = (double2 *)gc;
-  a.nb = nb;
-  a.s = s;
-  a.m = m;
-  a.batch = batch;
   a.M = (double2 *)wM;
   a.CQ = (double2 *)wO;
   a.X = a.CQ + (size_t)batch * 4 * ss2;
@@ -188,12 +189,10 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
     KernelScope ks_(ctx, "obc");
     hipLaunchKernelGGL(k_obc_cq, dim3(2 * tr * tc2, batch), dim3(T::NT), 0, ctx->stream, a);
   }
-  if (m > 0)
-    {
-      KernelScope ks_(ctx, "obc");
-      hipLaunchKernelGGL(k_obc_cqb, dim3(cdiv(2 * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0, ctx->stream,
-                         a);
-    }
+  if (m > 0) {
+    KernelScope ks_(ctx, "obc");
+    hipLaunchKernelGGL(k_obc_cqb, dim3(cdiv(2 * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0, ctx->stream, a);
+  }
   LuDesc d;
   d.nmat = batch;
   d.n = n;
@@ -209,19 +208,53 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
   d.ldx = nrhs;
   SS_TRY(lu_identity_perm(ctx, d));
   SS_TRY(lu_solve(ctx, d));
-  if (gc)
-    {
-      KernelScope ks_(ctx, "obc");
-      hipLaunchKernelGGL(k_obc_gc, dim3(cdiv(2 * s, T::BM) * tc2, batch), dim3(T::NT), 0, ctx->stream, a);
-    }
-  if (m > 0 && psi)
-    {
-      KernelScope ks_(ctx, "obc");
-      hipLaunchKernelGGL(k_obc_psi, dim3(cdiv(nb * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0,
-                         ctx->stream, a);
-    }
+  if (a.gc) {
+    KernelScope ks_(ctx, "obc");
+    hipLaunchKernelGGL(k_obc_gc, dim3(cdiv(2 * s, T::BM) * tc2, batch), dim3(T::NT), 0, ctx->stream, a);
+  }
+  if (m > 0 && want_psi) {
+    KernelScope ks_(ctx, "obc");
+    hipLaunchKernelGGL(k_obc_psi, dim3(cdiv(nb_max * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0,
+                       ctx->stream, a);
+  }
   hipLaunchKernelGGL(k_obc_info, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const int *)wZ, info, batch);
   return check_launch(ctx, "apply_obc");
+}
+
+ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
+                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+  ObcArgs a{};
+  a.Q = (const double2 *)Q;
+  a.sigma = (const double2 *)sigma;
+  a.inj = (const double2 *)inj;
+  a.psi = (double2 *)psi;
+  a.gc = (double2 *)gc;
+  a.nb = nb;
+  a.s = s;
+  a.m = m;
+  a.batch = batch;
+  a.nbv = nullptr;
+  a.boff = nullptr;
+  a.psi_tab = nullptr;
+  return obc_run(ctx, a, nb, psi != nullptr, info);
+}
+
+ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q, const ss_c128 *sigma, int m,
+                           const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info) {
+  ObcArgs a{};
+  a.Q = (const double2 *)Q;
+  a.sigma = (const double2 *)sigma;
+  a.inj = (const double2 *)inj;
+  a.psi = nullptr;
+  a.gc = (double2 *)gc;
+  a.nb = rb.nb_max;
+  a.s = rb.s;
+  a.m = m;
+  a.batch = rb.batch;
+  a.nbv = rb.nbv;
+  a.boff = rb.boff;
+  a.psi_tab = (double2 *const *)psi_tab;
+  return obc_run(ctx, a, rb.nb_max, psi_tab != nullptr, info);
 }
 
 // ------------------------------------------------------------------ transmission

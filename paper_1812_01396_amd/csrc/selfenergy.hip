@@ -21,6 +21,7 @@ namespace ss {
 
 struct DecArgs {
   const double2 *H00, *H01, *S00, *S01;  // [nk][s][s]
+  const double2 *const *tab;             // or per lead cell {H00, H01, S00, S01} pointers (null: stacked)
   const int *kidx;
   const double *E;
   double eta;
@@ -44,6 +45,13 @@ __device__ __forceinline__ int dec_set(const DecArgs &a, int inst) {
   return min(max(k, 0), a.nk - 1);
 }
 
+// block j (0 H00, 1 H01, 2 S00, 3 S01) of lead cell k
+__device__ __forceinline__ const double2 *dec_cell(const DecArgs &a, int k, int j) {
+  if (a.tab) return a.tab[4 * k + j];
+  const double2 *base = j == 0 ? a.H00 : j == 1 ? a.H01 : j == 2 ? a.S00 : a.S01;
+  return base + (long)k * a.s * a.s;
+}
+
 enum { kEps = 0, kEpsS = 1, kEpsL = 2, kAlpha0 = 3, kBeta0 = 5 };
 
 __device__ __forceinline__ double2 *dec_mat(const DecArgs &a, int inst, int which) {
@@ -60,8 +68,8 @@ __global__ void k_dec_init(DecArgs a) {
   const int ks = dec_set(a, inst);
   const double e = a.E[inst];
   const long ss2 = (long)s * s;
-  const double2 *h00 = a.H00 + ks * ss2, *s00 = a.S00 + ks * ss2;
-  const double2 *h01 = a.H01 + ks * ss2, *s01 = a.S01 + ks * ss2;
+  const double2 *h00 = dec_cell(a, ks, 0), *s00 = dec_cell(a, ks, 2);
+  const double2 *h01 = dec_cell(a, ks, 1), *s01 = dec_cell(a, ks, 3);
   double2 *M = a.M + (long)inst * 3 * ss2;
   double lmax = 0.0;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < ss2; idx += (long)gridDim.x * blockDim.x) {
@@ -203,8 +211,8 @@ __global__ void k_dec_final_form(DecArgs a, double2 *M2, const double2 *sigma, i
   const int ks = dec_set(a, inst);
   const double e = a.E[inst];
   const long ss2 = (long)s * s;
-  const double2 *h00 = a.H00 + ks * ss2, *s00 = a.S00 + ks * ss2;
-  const double2 *h01 = a.H01 + ks * ss2, *s01 = a.S01 + ks * ss2;
+  const double2 *h00 = dec_cell(a, ks, 0), *s00 = dec_cell(a, ks, 2);
+  const double2 *h01 = dec_cell(a, ks, 1), *s01 = dec_cell(a, ks, 3);
   const double2 *src = dec_mat(a, inst, side == 0 ? kEpsS : kEpsL);
   const double2 *sig = sigma + ((long)inst * 2 + (side == 0 ? 1 : 0)) * ss2;
   double2 *M = M2 + (long)sys * 2 * ss2;
@@ -249,10 +257,10 @@ __global__ void __launch_bounds__(DecTile::NT) k_dec_sigma(DecArgs a, const doub
   Acc<T> acc;
   acc.zero();
   if (side == 0) {
-    LdForm<false> la{a.H01 + ks * ss2, a.S01 + ks * ss2, s, e};
+    LdForm<false> la{dec_cell(a, ks, 1), dec_cell(a, ks, 3), s, e};
     mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
   } else {
-    LdForm<true> la{a.H01 + ks * ss2, a.S01 + ks * ss2, s, e};
+    LdForm<true> la{dec_cell(a, ks, 1), dec_cell(a, ks, 3), s, e};
     mma_loop<T>(la, lb, m0, s, n0, s, 0, s, acc, lds);
   }
   double d2 = 0.0, n2 = 0.0;
@@ -304,7 +312,7 @@ __global__ void k_dec_finish(DecArgs a, const double *acc2, int *iters, double *
 ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
                           const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
                           double eta, double tol, int max_iter, ss_c128 *sigma, int *iters, double *resid,
-                          int *info) {
+                          int *info, const ss_c128 *const *tab) {
   const long ss2 = (long)s * s;
   if (tol <= 0) tol = 1e-14;
   if (max_iter <= 0) max_iter = 200;
@@ -322,6 +330,7 @@ ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *
   a.H01 = (const double2 *)H01;
   a.S00 = (const double2 *)S00;
   a.S01 = (const double2 *)S01;
+  a.tab = (const double2 *const *)tab;
   a.kidx = kidx;
   a.E = E;
   a.eta = eta;

@@ -22,16 +22,19 @@ namespace ss {
 
 struct SweepArgs {
   const double2 *Hd, *Hu, *Sd, *Su;
-  long kstride_d, kstride_u;  // elements between consecutive (H, S) sets
+  long kstride_d, kstride_u;   // elements between consecutive (H, S) sets
+  const double2 *const *tab;   // or per set {H_diag, H_upper, S_diag, S_upper} pointers (null: strided)
   const int *kidx;
   const double *E;
   int nk, nb, s;
+  const int *nbv;    // per-instance block counts (null: every instance has nb blocks)
+  const long *boff;  // per-instance first block in the packed per-block stores (null: inst * nb)
   double2 *M;  // [nmat][s][2s]
   int *perm;   // [nmat][s]
   int *zp;     // [nmat]
   int *code;   // [batch] smallest zero-pivot code, INT_MAX if none
-  double2 *X;  // [nmat][nb][s][s]
-  double2 *Q;  // [batch][nb][s][2s]
+  double2 *X;  // per system: one s x s slot per block, packed (system 2i+d at block 2 boff(i) + d nb(i))
+  double2 *Q;  // per instance [nb][s][2s], packed at block boff(i)
   int *info;   // [batch] or null
   int batch;
 };
@@ -41,6 +44,22 @@ struct SweepArgs {
 __device__ __forceinline__ int set_of(const SweepArgs &a, int inst) {
   const int k = a.kidx ? a.kidx[inst] : inst % a.nk;
   return min(max(k, 0), a.nk - 1);
+}
+__device__ __forceinline__ int nb_of(const SweepArgs &a, int inst) { return a.nbv ? a.nbv[inst] : a.nb; }
+__device__ __forceinline__ long boff_of(const SweepArgs &a, int inst) {
+  return a.boff ? a.boff[inst] : (long)inst * a.nb;
+}
+// block b of array j (0 H_diag, 1 H_upper, 2 S_diag, 3 S_upper) of set k
+__device__ __forceinline__ const double2 *blk(const SweepArgs &a, int k, int j, int b) {
+  const long ss2 = (long)a.s * a.s;
+  if (a.tab) return a.tab[4 * k + j] + b * ss2;
+  const double2 *base = j == 0 ? a.Hd : j == 1 ? a.Hu : j == 2 ? a.Sd : a.Su;
+  return base + k * ((j & 1) ? a.kstride_u : a.kstride_d) + b * ss2;
+}
+// slot t of system mat
+__device__ __forceinline__ double2 *xslot(const SweepArgs &a, int mat, int t) {
+  const int inst = mat >> 1, dir = mat & 1;
+  return a.X + (2 * boff_of(a, inst) + (long)dir * nb_of(a, inst) + t) * ((long)a.s * a.s);
 }
 
 using FormTile = TileCfg<64, 64, 16, 2, 2>;
@@ -71,13 +90,14 @@ __global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
-  const int s = a.s, nb = a.nb;
+  const int s = a.s, nb = nb_of(a, inst);
+  if (t >= nb) return;
   const int ks = set_of(a, inst);
   const double e = a.E[inst];
   const int ib = dir == 0 ? nb - 1 - t : t;
   const long ss2 = (long)s * s;
-  const double2 *hd = a.Hd + ks * a.kstride_d + ib * ss2;
-  const double2 *sd = a.Sd + ks * a.kstride_d + ib * ss2;
+  const double2 *hd = blk(a, ks, 0, ib);
+  const double2 *sd = blk(a, ks, 2, ib);
   double2 *M = a.M + (long)mat * 2 * ss2;
   const int tiles = cdiv(s, T::BM);
   const int ntile = tiles * tiles;
@@ -103,14 +123,13 @@ __global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
       }
     };
     if (t > 0) {
-      const double2 *xp = a.X + ((long)mat * nb + (t - 1)) * ss2;
+      const double2 *xp = xslot(a, mat, t - 1);
       LdRow lb{xp, s};
       if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
-        LdForm<false> la{a.Hu + ks * a.kstride_u + ib * ss2, a.Su + ks * a.kstride_u + ib * ss2, s, e};
+        LdForm<false> la{blk(a, ks, 1, ib), blk(a, ks, 3, ib), s, e};
         tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
       } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
-        LdForm<true> la{a.Hu + ks * a.kstride_u + (ib - 1) * ss2, a.Su + ks * a.kstride_u + (ib - 1) * ss2,
-                        s, e};
+        LdForm<true> la{blk(a, ks, 1, ib - 1), blk(a, ks, 3, ib - 1), s, e};
         tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
       }
     } else {
@@ -127,8 +146,8 @@ __global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
     const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
     const bool ident = dir == 0 ? ib == 0 : ib == nb - 1;
     const int ub = dir == 0 ? ib - 1 : ib;
-    const double2 *hu = a.Hu + ks * a.kstride_u + (long)std::max(ub, 0) * ss2;
-    const double2 *su = a.Su + ks * a.kstride_u + (long)std::max(ub, 0) * ss2;
+    const double2 *hu = blk(a, ks, 1, std::max(ub, 0));
+    const double2 *su = blk(a, ks, 3, std::max(ub, 0));
     for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
       const int r = idx / T::BN, c = idx % T::BN;
       const int gr = m0 + r, gc = n0 + c;
@@ -155,7 +174,7 @@ __global__ void k_sweep_finish(SweepArgs a) {
   for (int dir = 0; dir < 2; ++dir) {
     const int z = a.zp[2 * inst + dir];
     if (z != 0) {
-      const int pib = dir == 0 ? 0 : a.nb - 1;
+      const int pib = dir == 0 ? 0 : nb_of(a, inst) - 1;
       c = min(c, pib * a.s + z);
     }
   }
@@ -173,13 +192,15 @@ __global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
-  const int s = a.s, nb = a.nb;
+  const int s = a.s, nb = nb_of(a, inst);
+  if (u >= nb) return;
   const long ss2 = (long)s * s;
   const int tiles = cdiv(s, T::BM);
   const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
   const int ib = dir == 0 ? u : nb - 1 - u;
-  const double2 *x = a.X + ((long)mat * nb + (nb - 1 - u)) * ss2;
-  double2 *qi = a.Q + (long)inst * nb * 2 * ss2 + (long)ib * 2 * ss2 + (dir ? s : 0);
+  const double2 *x = xslot(a, mat, nb - 1 - u);
+  double2 *q0 = a.Q + boff_of(a, inst) * 2 * ss2 + (dir ? s : 0);
+  double2 *qi = q0 + (long)ib * 2 * ss2;
   if (u == 0) {
     for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
       const int gr = m0 + idx / T::BN, gc = n0 + idx % T::BN;
@@ -188,7 +209,7 @@ __global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
     return;
   }
   const int pb = dir == 0 ? ib - 1 : ib + 1;
-  const double2 *qp = a.Q + (long)inst * nb * 2 * ss2 + (long)pb * 2 * ss2 + (dir ? s : 0);
+  const double2 *qp = q0 + (long)pb * 2 * ss2;
   LdRow la{x, s};
   LdRow lb{qp, 2 * s};
   tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
@@ -201,52 +222,39 @@ __global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
 // map) for later solves with the same diagonal systems.
 __global__ void k_save_factors(SweepArgs a, double2 *F, int *P, int t) {
   const int inst = blockIdx.y, s = a.s;
+  if (t >= nb_of(a, inst)) return;
   const long ss2 = (long)s * s;
   const double2 *M = a.M + (long)(2 * inst) * 2 * ss2;
-  double2 *f = F + ((long)inst * a.nb + t) * ss2;
+  const long blk_t = boff_of(a, inst) + t;
+  double2 *f = F + blk_t * ss2;
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < ss2; idx += (long)gridDim.x * blockDim.x) {
     const int r = idx / s, c = idx % s;
     f[idx] = M[(long)r * 2 * s + c];
   }
   if (blockIdx.x == 0)
-    for (int r = threadIdx.x; r < s; r += blockDim.x) P[((long)inst * a.nb + t) * s + r] = a.perm[(long)(2 * inst) * s + r];
+    for (int r = threadIdx.x; r < s; r += blockDim.x) P[blk_t * s + r] = a.perm[(long)(2 * inst) * s + r];
 }
 
-ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
-                             int flags, ss_c128 *Q, int *info) {
-  const int s = hs->s, nb = hs->nb, nmat = 2 * batch;
+// Enqueue both recursions and chains.  act[t] is the number of leading instances with more than t
+// blocks (instances come sorted by block count, largest first), so step t runs on that prefix only.
+// xoff: per-system X offsets for ragged batches (null when every instance has a.nb blocks).
+static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &act, long total_blocks,
+                           const long *xoff, int prec, bool keep) {
+  const int s = a.s, batch = a.batch, nmat = 2 * batch, nsteps = (int)act.size();
   const long ss2 = (long)s * s;
   const int n = s, nrhs = s, ldm = 2 * s;
-  void *wM, *wP, *wZ, *wX, *wC;
+  void *wM, *wP, *wZ, *wX;
   SS_TRY(workspace(ctx, kSlotM, sizeof(double2) * nmat * (size_t)n * ldm, &wM));
   SS_TRY(workspace(ctx, kSlotPerm, sizeof(int) * nmat * (size_t)n, &wP));
   SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)(nmat + batch), &wZ));
-  SS_TRY(workspace(ctx, kSlotX, sizeof(double2) * nmat * (size_t)nb * ss2, &wX));
-  wC = (int *)wZ + nmat;
-
-  SweepArgs a;
-  a.Hd = (const double2 *)hs->H_diag;
-  a.Hu = (const double2 *)hs->H_upper;
-  a.Sd = (const double2 *)hs->S_diag;
-  a.Su = (const double2 *)hs->S_upper;
-  a.kstride_d = (long)nb * ss2;
-  a.kstride_u = (long)std::max(nb - 1, 0) * ss2;
-  a.kidx = kidx;
-  a.E = E;
-  a.nk = hs->nk;
-  a.nb = nb;
-  a.s = s;
+  SS_TRY(workspace(ctx, kSlotX, sizeof(double2) * 2 * (size_t)total_blocks * ss2, &wX));
   a.M = (double2 *)wM;
   a.perm = (int *)wP;
   a.zp = (int *)wZ;
-  a.code = (int *)wC;
+  a.code = (int *)wZ + nmat;
   a.X = (double2 *)wX;
-  a.Q = (double2 *)Q;
-  a.info = info;
-  a.batch = batch;
 
   LuDesc d;
-  d.nmat = nmat;
   d.n = n;
   d.nrhs = nrhs;
   d.M = a.M;
@@ -255,49 +263,98 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   d.perm = a.perm;
   d.sP = n;
   d.zp = a.zp;
-  d.sX = (long)nb * ss2;
+  d.sX = (long)a.nb * ss2;
+  d.xoff = xoff;
   d.ldx = s;
 
   double2 *F = nullptr;
   int *P = nullptr;
-  const bool keep = (flags & SS_KEEP_FACTORS) != 0;
   if (keep) {
-    SS_TRY(workspace(ctx, kSlotFact, sizeof(double2) * (size_t)batch * nb * ss2, (void **)&F));
-    SS_TRY(workspace(ctx, kSlotFactPerm, sizeof(int) * (size_t)batch * nb * s, (void **)&P));
+    SS_TRY(workspace(ctx, kSlotFact, sizeof(double2) * (size_t)total_blocks * ss2, (void **)&F));
+    SS_TRY(workspace(ctx, kSlotFactPerm, sizeof(int) * (size_t)total_blocks * s, (void **)&P));
   }
   ctx->fact_valid = false;
   const bool f32 = prec == SS_PREC_FP32;
   hipLaunchKernelGGL(k_code_init, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a.code, batch);
   const int tiles = cdiv(s, FormTile::BM);
-  for (int t = 0; t < nb; ++t) {
+  for (int t = 0; t < nsteps; ++t) {
+    const int na = act[t];
+    if (na <= 0) break;
     {
       KernelScope ks_(ctx, "form");
       if (f32)
-        hipLaunchKernelGGL(k_form<true>, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
+        hipLaunchKernelGGL(k_form<true>, dim3(2 * tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, t);
       else
-        hipLaunchKernelGGL(k_form<false>, dim3(2 * tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, t);
+        hipLaunchKernelGGL(k_form<false>, dim3(2 * tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a,
+                           t);
     }
+    d.nmat = 2 * na;
     d.X = a.X + (long)t * ss2;
     SS_TRY(lu_solve(ctx, d));
     if (keep)
-      hipLaunchKernelGGL(k_save_factors, dim3(std::min(cdiv((int)std::min<long>(ss2, 1 << 30), 256), 64), batch),
+      hipLaunchKernelGGL(k_save_factors, dim3(std::min(cdiv((int)std::min<long>(ss2, 1 << 30), 256), 64), na),
                          dim3(256), 0, ctx->stream, a, F, P, t);
   }
   hipLaunchKernelGGL(k_sweep_finish, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a);
-  for (int u = 0; u < nb; ++u) {
+  for (int u = 0; u < nsteps; ++u) {
+    const int na = act[u];
+    if (na <= 0) break;
     KernelScope ks_(ctx, "chain");
     if (f32)
-      hipLaunchKernelGGL(k_chain<true>, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
+      hipLaunchKernelGGL(k_chain<true>, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, u);
     else
-      hipLaunchKernelGGL(k_chain<false>, dim3(tiles * tiles, nmat), dim3(FormTile::NT), 0, ctx->stream, a, u);
+      hipLaunchKernelGGL(k_chain<false>, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, u);
   }
+  return check_launch(ctx, "precompute_columns");
+}
+
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
+                             int flags, ss_c128 *Q, int *info) {
+  const int s = hs->s, nb = hs->nb;
+  const long ss2 = (long)s * s;
+  SweepArgs a{};
+  a.Hd = (const double2 *)hs->H_diag;
+  a.Hu = (const double2 *)hs->H_upper;
+  a.Sd = (const double2 *)hs->S_diag;
+  a.Su = (const double2 *)hs->S_upper;
+  a.kstride_d = (long)nb * ss2;
+  a.kstride_u = (long)std::max(nb - 1, 0) * ss2;
+  a.tab = nullptr;
+  a.kidx = kidx;
+  a.E = E;
+  a.nk = hs->nk;
+  a.nb = nb;
+  a.s = s;
+  a.nbv = nullptr;
+  a.boff = nullptr;
+  a.Q = (double2 *)Q;
+  a.info = info;
+  a.batch = batch;
+  const bool keep = (flags & SS_KEEP_FACTORS) != 0;
+  SS_TRY(sweep_run(ctx, a, std::vector<int>(nb, batch), (long)batch * nb, nullptr, prec, keep));
   if (keep) {
     ctx->fact_valid = true;
     ctx->fact_batch = batch;
     ctx->fact_nb = nb;
     ctx->fact_s = s;
   }
-  return check_launch(ctx, "precompute_columns");
+  return SS_OK;
+}
+
+ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, int prec, ss_c128 *Q, int *info) {
+  SweepArgs a{};
+  a.tab = (const double2 *const *)rb.tab;
+  a.kidx = nullptr;
+  a.E = rb.E;
+  a.nk = rb.batch;
+  a.nb = rb.nb_max;
+  a.s = rb.s;
+  a.nbv = rb.nbv;
+  a.boff = rb.boff;
+  a.Q = (double2 *)Q;
+  a.info = info;
+  a.batch = rb.batch;
+  return sweep_run(ctx, a, rb.act, rb.total_blocks, rb.xoff, prec, false);
 }
 
 }  // namespace ss

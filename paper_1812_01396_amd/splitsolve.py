@@ -24,7 +24,8 @@ EXPORTS = (
     "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_synchronize", "ss_status_string", "ss_last_error",
     "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
-    "ss_transmission_psi",
+    "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
+    "ss_plan_graph_nodes", "ss_plan_destroy",
 )
 
 
@@ -39,6 +40,24 @@ class _Btd(ctypes.Structure):
         ("nb", ctypes.c_int), ("s", ctypes.c_int), ("nk", ctypes.c_int),
         ("H_diag", ctypes.c_void_p), ("H_upper", ctypes.c_void_p),
         ("S_diag", ctypes.c_void_p), ("S_upper", ctypes.c_void_p),
+    ]
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [
+        ("nb", ctypes.c_int), ("s", ctypes.c_int), ("E", ctypes.c_double),
+        ("H_diag", ctypes.c_void_p), ("H_upper", ctypes.c_void_p),
+        ("S_diag", ctypes.c_void_p), ("S_upper", ctypes.c_void_p),
+        ("H00", ctypes.c_void_p), ("H01", ctypes.c_void_p), ("S00", ctypes.c_void_p), ("S01", ctypes.c_void_p),
+        ("psi", ctypes.c_void_p),
+    ]
+
+
+class _PlanOpts(ctypes.Structure):
+    _fields_ = [
+        ("eta", ctypes.c_double), ("sigma_tol", ctypes.c_double), ("sigma_passes", ctypes.c_int),
+        ("m", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
+        ("mem_bytes", ctypes.c_size_t),
     ]
 
 
@@ -89,6 +108,20 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_refine_psi.restype = I
     lib.ss_transmission_psi.argtypes = [P, I, I, I, I, P, P, P]
     lib.ss_transmission_psi.restype = I
+    lib.ss_plan_create.argtypes = [P, I, ctypes.POINTER(_Instance), ctypes.POINTER(_PlanOpts), P, P,
+                                   ctypes.POINTER(P)]
+    lib.ss_plan_create.restype = I
+    lib.ss_plan_execute.argtypes = [P]
+    lib.ss_plan_execute.restype = I
+    lib.ss_plan_groups.argtypes = [P]
+    lib.ss_plan_groups.restype = I
+    lib.ss_plan_describe.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
+                                     ctypes.POINTER(I), ctypes.POINTER(D)]
+    lib.ss_plan_describe.restype = I
+    lib.ss_plan_graph_nodes.argtypes = [P]
+    lib.ss_plan_graph_nodes.restype = ctypes.c_longlong
+    lib.ss_plan_destroy.argtypes = [P]
+    lib.ss_plan_destroy.restype = None
     _lib = lib
     return lib
 
@@ -319,3 +352,89 @@ def ss_transmission_psi(ctx: Context, psi, sigma, T=None):
     T = T if T is not None else torch.empty(batch, dtype=torch.float64, device=dev)
     ctx.check(ctx.lib.ss_transmission_psi(ctx.handle, batch, nb, s, m, _ptr(psi), _ptr(sigma), _ptr(T)))
     return T
+
+
+class Instance:
+    """One (E, k) instance of an uneven batch: device tensors of its blocks and lead cell.
+
+    Hd [nb][s][s], Hu [nb-1][s][s], Sd, Su likewise; H00, H01, S00, S01 [s][s]; psi [nb][s][m] or None.
+    """
+
+    def __init__(self, Hd, Hu, Sd, Su, H00, H01, S00, S01, E, psi=None):
+        self.Hd, self.Hu, self.Sd, self.Su = Hd, Hu, Sd, Su
+        self.H00, self.H01, self.S00, self.S01 = H00, H01, S00, S01
+        self.E = float(E)
+        self.psi = psi
+        self.nb, self.s = int(Hd.shape[0]), int(Hd.shape[1])
+
+
+class Plan:
+    """ss_plan over a list of Instance objects; keeps every tensor it was built from alive.
+
+    T [n][2] float64 and info [n][3] int32 (device) are written by every ``execute()``.
+    """
+
+    def __init__(self, ctx: Context, instances, eta: float, m: int = 0, use_graph: bool = True,
+                 autotune: bool = True, sigma_tol: float = 0.0, sigma_passes: int = 0, mem_bytes: int = 0):
+        dev = ctx.device
+        n = len(instances)
+        if n < 1:
+            raise ValueError("a plan needs at least one instance")
+        arr = (_Instance * n)()
+        for i, x in enumerate(instances):
+            nb, s = x.nb, x.s
+            if s < 1 or s > SS_MAX_S or nb < 1:
+                raise ValueError(f"instance {i}: unsupported sizes nb={nb}, s={s}")
+            _need(x.Hd, torch.complex128, dev, f"instance {i} Hd", (nb, s, s))
+            _need(x.Sd, torch.complex128, dev, f"instance {i} Sd", (nb, s, s))
+            _need(x.Hu, torch.complex128, dev, f"instance {i} Hu", (nb - 1, s, s))
+            _need(x.Su, torch.complex128, dev, f"instance {i} Su", (nb - 1, s, s))
+            for nm in ("H00", "H01", "S00", "S01"):
+                _need(getattr(x, nm), torch.complex128, dev, f"instance {i} {nm}", (s, s))
+            if x.psi is not None:
+                if m < 1:
+                    raise ValueError("psi requested with m = 0")
+                _need(x.psi, torch.complex128, dev, f"instance {i} psi", (nb, s, m))
+            arr[i] = _Instance(nb, s, x.E, x.Hd.data_ptr(), x.Hu.data_ptr() if nb > 1 else None, x.Sd.data_ptr(),
+                               x.Su.data_ptr() if nb > 1 else None, x.H00.data_ptr(), x.H01.data_ptr(),
+                               x.S00.data_ptr(), x.S01.data_ptr(), None if x.psi is None else x.psi.data_ptr())
+        opts = _PlanOpts(float(eta), float(sigma_tol), int(sigma_passes), int(m), int(bool(use_graph)),
+                         int(bool(autotune)), int(mem_bytes))
+        self.ctx = ctx
+        self.instances = list(instances)
+        self.T = torch.zeros(n, 2, dtype=torch.float64, device=dev)
+        self.info = torch.zeros(n, 3, dtype=torch.int32, device=dev)
+        h = ctypes.c_void_p()
+        ctx.check(ctx.lib.ss_plan_create(ctx.handle, n, arr, ctypes.byref(opts), _ptr(self.T), _ptr(self.info),
+                                         ctypes.byref(h)))
+        self.handle = h
+
+    def execute(self):
+        self.ctx.check(self.ctx.lib.ss_plan_execute(self.handle))
+
+    @property
+    def graph_nodes(self) -> int:
+        return int(self.ctx.lib.ss_plan_graph_nodes(self.handle))
+
+    def groups(self):
+        """Per group: dict(s, count, chunk, lu_width, tune_ms)."""
+        out = []
+        lib = self.ctx.lib
+        for g in range(lib.ss_plan_groups(self.handle)):
+            s, c, ch, w = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+            ms = ctypes.c_double()
+            self.ctx.check(lib.ss_plan_describe(self.handle, g, ctypes.byref(s), ctypes.byref(c), ctypes.byref(ch),
+                                                ctypes.byref(w), ctypes.byref(ms)))
+            out.append(dict(s=s.value, count=c.value, chunk=ch.value, lu_width=w.value, tune_ms=ms.value))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.ss_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

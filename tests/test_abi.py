@@ -56,6 +56,12 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.ss_transmission(None, 1, 4, None, None, None) == 1
     assert lib.ss_synchronize(None) == 1
     assert lib.ss_workspace_bytes(None) == 0
+    assert lib.ss_plan_create(None, 1, None, None, None, None, None) == 1
+    assert lib.ss_plan_execute(None) == 1
+    assert lib.ss_plan_groups(None) == 0
+    assert lib.ss_plan_graph_nodes(None) == 0
+    assert lib.ss_plan_describe(None, 0, None, None, None, None, None) == 1
+    lib.ss_plan_destroy(None)
 
 
 @pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-GPU path")

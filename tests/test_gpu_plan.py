@@ -1,0 +1,149 @@
+"""Uneven batches (ss_plan_*) against the oracle, and graph replays against eager execution.
+
+A plan mixes block sizes s and block counts nb (nb = 1 included), each instance with its own cell.
+Checked per instance: info codes, T_LR and T_RL against the oracle's Caroli T, and the wave function
+through the quantity that does not depend on the choice of injection factor W_L (W_L W_L^H = Gamma_L):
+psi psi^H = G_{:,1} Gamma_L G_{:,1}^H, against the oracle's psi for its own factor of Gamma_L.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import selfenergy, transport
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+UNIT = 2.0 ** -52
+ETA = 1e-8
+SIZES = [(16, 3), (40, 5), (16, 1), (72, 2), (24, 6), (40, 2), (16, 4), (72, 3), (24, 1), (40, 4)]
+
+
+def _dev(a, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1812_01396_amd as ss
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = ss.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def batch():
+    rng = np.random.default_rng(31)
+    insts = [synth.random_btd(nb, s, seed=500 + i) for i, (s, nb) in enumerate(SIZES)]
+    Es = rng.uniform(-0.6, 0.6, len(SIZES))
+    return insts, Es
+
+
+def _make(ss, insts, Es, m):
+    out = []
+    for inst, E in zip(insts, Es):
+        nb, s = inst.Hd.shape[0], inst.Hd.shape[1]
+        hu = inst.Hu if nb > 1 else np.zeros((0, s, s), np.complex128)
+        su = inst.Su if nb > 1 else np.zeros((0, s, s), np.complex128)
+        psi = torch.zeros(nb, s, m, dtype=torch.complex128, device="cuda") if m else None
+        out.append(ss.Instance(_dev(inst.Hd), _dev(hu), _dev(inst.Sd), _dev(su), _dev(inst.H00), _dev(inst.H01),
+                               _dev(inst.S00), _dev(inst.S01), E, psi))
+    return out
+
+
+def _tolerance(inst, E):
+    a0, a1, am1 = selfenergy.lead_blocks(inst.H00, inst.H01, inst.S00, inst.S01, E, ETA)
+    return max(TOL, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1))
+
+
+def _gamma_factor(inst, E):
+    """A factor W of the oracle's Gamma_L (eigenvectors scaled by sqrt of the positive eigenvalues)."""
+    a0, a1, am1 = selfenergy.lead_blocks(inst.H00, inst.H01, inst.S00, inst.S01, E, ETA)
+    sl, _, _, _ = selfenergy.decimation(a0, a1, am1)
+    lam, v = np.linalg.eigh(selfenergy.broadening(sl))
+    keep = lam > 1e-12 * max(lam.max(), 1e-300)
+    return v[:, keep] * np.sqrt(lam[keep])
+
+
+@pytest.mark.parametrize("use_graph,autotune", [(True, True), (False, False)])
+def test_plan_matches_oracle(ctx, batch, use_graph, autotune):
+    import paper_1812_01396_amd as ss
+    insts, Es = batch
+    m = max(s for s, _ in SIZES)
+    print(f"plan vs oracle graph={use_graph} autotune={autotune}", flush=True)
+    xs = _make(ss, insts, Es, m)
+    plan = ss.Plan(ctx, xs, ETA, m=m, use_graph=use_graph, autotune=autotune)
+    plan.execute()
+    torch.cuda.synchronize()
+    T = plan.T.cpu().numpy()
+    info = plan.info.cpu().numpy()
+    assert (info == 0).all(), info
+    assert sorted(g["s"] for g in plan.groups()) == sorted({s for s, _ in SIZES})
+    for i, (inst, E) in enumerate(zip(insts, Es)):
+        tol = _tolerance(inst, E)
+        W = _gamma_factor(inst, E)
+        nb, s = inst.Hd.shape[0], inst.Hd.shape[1]
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00, inst.S01,
+                                       E, ETA, inj=np.vstack([W, np.zeros_like(W)]) if W.shape[1] else None,
+                                       want_q=False)
+        for got, want in ((T[i, 0], ref["t_lr"]), (T[i, 1], ref["t_rl"])):
+            assert abs(got - want) <= tol * max(1.0, abs(want)), (i, got, want, tol)
+        psi = xs[i].psi.cpu().numpy().reshape(nb * s, m)
+        P = psi @ psi.conj().T
+        if W.shape[1]:
+            pr = ref["psi"].reshape(nb * s, -1)
+            Pref = pr @ pr.conj().T
+            assert _rel(P, Pref) <= max(1e-9, tol), (i, _rel(P, Pref))
+        else:
+            assert np.abs(P).max() == 0.0
+    plan.close()
+
+
+def test_plan_graph_replays_match_eager(ctx, batch):
+    """Several replays of the captured graph, with other GPU work in between, against an eager plan."""
+    import paper_1812_01396_amd as ss
+    insts, Es = batch
+    m = 8
+    xe = _make(ss, insts, Es, m)
+    eager = ss.Plan(ctx, xe, ETA, m=m, use_graph=False, autotune=False)
+    eager.execute()
+    torch.cuda.synchronize()
+    T0 = eager.T.cpu().numpy()
+    psi0 = [x.psi.cpu().numpy() for x in xe]
+    xg = _make(ss, insts, Es, m)
+    graph = ss.Plan(ctx, xg, ETA, m=m, use_graph=True, autotune=False)
+    assert graph.graph_nodes > 0
+    for rep in range(3):
+        graph.T.zero_()
+        for x in xg:
+            x.psi.zero_()
+        junk = torch.randn(512, 512, device="cuda") @ torch.randn(512, 512, device="cuda")
+        graph.execute()
+        torch.cuda.synchronize()
+        assert float(junk.abs().sum()) > 0
+        assert np.abs(graph.T.cpu().numpy() - T0).max() <= 1e-13, rep
+        assert (graph.info.cpu().numpy() == 0).all()
+        for x, p0 in zip(xg, psi0):
+            assert _rel(x.psi.cpu().numpy(), p0) <= 1e-13, rep
+    graph.close()
+    eager.close()
+
+
+def test_plan_small_memory_runs_one_instance_per_chunk(ctx, batch):
+    import paper_1812_01396_amd as ss
+    insts, Es = batch
+    big = ss.Plan(ctx, _make(ss, insts, Es, 0), ETA, use_graph=False, autotune=False)
+    small = ss.Plan(ctx, _make(ss, insts, Es, 0), ETA, use_graph=False, autotune=False, mem_bytes=1)
+    assert all(g["chunk"] == 1 for g in small.groups())
+    big.execute()
+    small.execute()
+    torch.cuda.synchronize()
+    assert np.abs(big.T.cpu().numpy() - small.T.cpu().numpy()).max() <= 1e-12
+    big.close()
+    small.close()
