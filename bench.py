@@ -15,6 +15,9 @@ Workloads (synthetic, seeded; see synth/):
            k in {pi/8, 3pi/8, 5pi/8, 7pi/8}, seed 1, crystal device, complex128   (default)
   chain16  s = 16 random chain cell, nb = 32, 64 energies in [-3, 3], seed 0, complex128
   dft1024  s = 1024 (8x8x16 slab), nb = 60, 32 energies in [-5, 5] eV, k = pi/3, seed 2
+  uneven256  256 instances, each its own lattice-slab crystal: s uniform in {128, 256, 384, 512, 768},
+           nb uniform in [16, 64], E uniform in [-5, 5] eV, k uniform in [0, pi); instance i draws from
+           numpy default_rng([3, i]); run as one plan (per-size groups, graph replay, autotuned)
 
 Prints one JSON line.  --gpus > 1 is refused: this build measures one GPU.
 """
@@ -42,6 +45,8 @@ WORKLOADS = {
     "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=16),
 }
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
+UNEVEN = dict(n=256, sizes=(128, 256, 384, 512, 768), nb_lo=16, nb_hi=64, e_lo=-5.0, e_hi=5.0, seed=3, eta=1e-8,
+              m=32)
 
 
 def sweep_flops(nb: int, s: int) -> float:
@@ -106,6 +111,140 @@ def cpu_baseline(w, insts, E, kidx, inj, sample: int, T_gpu):
     return dict(value=len(idx) / dt, unit="solves/s", cores=int(cores), kind="oracle",
                 sample=f"{len(idx)} of {len(E)} instances (indices {idx.tolist()}), same inputs, "
                        f"{dt:.1f} s wall"), float(max(errs))
+
+
+def uneven_specs(n: int = UNEVEN["n"], seed: int = UNEVEN["seed"]):
+    """(s, nb, E, k, cell_seed) of every instance of the uneven batch; instance i from default_rng([seed, i])."""
+    u = UNEVEN
+    out = []
+    for i in range(n):
+        rng = np.random.default_rng([seed, i])
+        s = int(rng.choice(u["sizes"]))
+        nb = int(rng.integers(u["nb_lo"], u["nb_hi"] + 1))
+        E = float(rng.uniform(u["e_lo"], u["e_hi"]))
+        k = float(rng.uniform(0.0, np.pi))
+        out.append((s, nb, E, k, int(rng.integers(2**31))))
+    return out
+
+
+def uneven_cell(spec):
+    import synth
+    s, nb, E, k, cs = spec
+    return synth.DFTLikeCell(synth.SLAB_SHAPES[s], cs).at(k)
+
+
+class UnevenPipeline:
+    """The uneven batch as one ss_plan: crystal devices (every block a copy of the instance's own cell,
+    materialised on the GPU), psi for m columns per instance; run() is one plan execution."""
+
+    def __init__(self, n: int = UNEVEN["n"], use_graph: bool = True, autotune: bool = True, mem_gib: float = 32.0):
+        import torch
+
+        import paper_1812_01396_amd as ss
+
+        self.ss, self.torch = ss, torch
+        self.specs = uneven_specs(n)
+        self.w = dict(UNEVEN, n=n)
+        m = self.w["m"]
+        dev = torch.device("cuda", 0)
+        self.ctx = ss.Context(0)
+        self.instances = []
+        for spec in self.specs:
+            s, nb, E, k, _ = spec
+            h00, h01, s00, s01 = (torch.as_tensor(a).to(dev) for a in uneven_cell(spec))
+            x = ss.Instance(h00.expand(nb, s, s).contiguous(), h01.expand(nb - 1, s, s).contiguous(),
+                            s00.expand(nb, s, s).contiguous(), s01.expand(nb - 1, s, s).contiguous(),
+                            h00, h01, s00, s01, E, torch.zeros(nb, s, m, dtype=torch.complex128, device=dev))
+            self.instances.append(x)
+        t0 = time.perf_counter()
+        self.plan = ss.Plan(self.ctx, self.instances, self.w["eta"], m=m, use_graph=use_graph, autotune=autotune,
+                            mem_bytes=int(mem_gib * (1 << 30)))
+        torch.cuda.synchronize()
+        self.create_s = time.perf_counter() - t0
+
+    def run(self):
+        self.plan.execute()
+
+
+def run_uneven(args):
+    import torch
+
+    pipe = UnevenPipeline(use_graph=not args.no_graph, autotune=not args.no_autotune, mem_gib=args.plan_mem_gib)
+    for _ in range(args.warmup):
+        pipe.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pipe.run()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    T = pipe.plan.T.cpu().numpy()
+    info = pipe.plan.info.cpu().numpy()
+    m = pipe.w["m"]
+    f_step = sum(sweep_flops(nb, s) + dec_flops(s, float(info[i, 3])) + obc_flops(nb, s, m)
+                 for i, (s, nb, _, _, _) in enumerate(pipe.specs))
+    f_sweep = sum(sweep_flops(nb, s) for (s, nb, _, _, _) in pipe.specs)
+    ms_per_step = elapsed * 1e3 / args.steps
+    achieved = f_step / (ms_per_step * 1e-3) / 1e12
+    cpu, t_err = None, None
+    if not args.no_cpu_baseline and args.cpu_sample > 0:
+        from oracle import transport
+        import synth
+        # the smallest instances keep the oracle's share of the run bounded
+        order = sorted(range(len(pipe.specs)), key=lambda i: pipe.specs[i][0] ** 3 * pipe.specs[i][1])
+        idx = order[: args.cpu_sample]
+        t0 = time.perf_counter()
+        errs = []
+        for i in idx:
+            s, nb, E, k, _ = pipe.specs[i]
+            inst = synth.device_from_cell(uneven_cell(pipe.specs[i]), nb)
+            ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
+                                           inst.S01, E, pipe.w["eta"], want_q=False)
+            errs.append(max(abs(T[i, 0] - ref["t_lr"]), abs(T[i, 1] - ref["t_rl"])) / max(1.0, abs(ref["t_lr"])))
+        dt = time.perf_counter() - t0
+        try:
+            import threadpoolctl
+            cores = max(p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()) or os.cpu_count()
+        except Exception:
+            cores = os.cpu_count()
+        cpu = dict(value=len(idx) / dt, unit="solves/s", cores=int(cores), kind="oracle",
+                   sample=f"{len(idx)} smallest of {len(pipe.specs)} instances (indices {idx}), {dt:.1f} s wall; "
+                          "not representative of the mean instance")
+        t_err = float(max(errs))
+    groups = pipe.plan.groups()
+    out = {
+        "metric": "(E,k) solves/sec",
+        "value": round(len(pipe.specs) * args.steps / elapsed, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128",
+        "data": "synthetic",
+        "config": {"workload": "uneven256", "instances": len(pipe.specs), "sizes": list(UNEVEN["sizes"]),
+                   "nb_range": [UNEVEN["nb_lo"], UNEVEN["nb_hi"]], "m_inj": m, "eta": UNEVEN["eta"],
+                   "graph": not args.no_graph, "autotune": not args.no_autotune, "plan_mem_gib": args.plan_mem_gib,
+                   "precision": "fp64"},
+        "tflops_step": round(achieved, 3),
+        "sweep_tflop": round(f_sweep / 1e12, 2),
+        "step_tflop": round(f_step / 1e12, 2),
+        "roofline": dict(bound="mfma", achieved=round(achieved, 3), peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                         frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None, kernel="whole step"),
+        "plan_create_s": round(pipe.create_s, 2),
+        "graph_nodes": pipe.plan.graph_nodes,
+        "groups": groups,
+        "decimation_iters": [int(info[:, 3].min()), int(info[:, 3].max())],
+        "nonzero_info": int((info[:, :3] != 0).sum()),
+        "t_lr_minus_t_rl_max": float(np.abs(T[:, 0] - T[:, 1]).max()),
+        "t_minus_integer_max": float(np.abs(T - np.round(T)).max()),
+        "cpu_baseline": cpu,
+        "t_err_vs_oracle": t_err,
+    }
+    print(json.dumps(out))
 
 
 class Pipeline:
@@ -213,7 +352,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS) + ["uneven256"])
+    ap.add_argument("--no-graph", action="store_true", help="uneven256: enqueue eagerly instead of a graph replay")
+    ap.add_argument("--no-autotune", action="store_true", help="uneven256: default panel widths and chunks")
+    ap.add_argument("--plan-mem-gib", type=float, default=32.0, help="uneven256: chunk work memory")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
     ap.add_argument("--roofline-kernel", default="dec_update",
@@ -229,6 +371,8 @@ def main():
 
     import torch
 
+    if args.workload == "uneven256":
+        return run_uneven(args)
     pipe = Pipeline(args.workload, args.chunk, args.mode)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel

@@ -229,9 +229,9 @@ typedef struct {
 
 typedef struct ss_plan ss_plan;
 
-/* Build a plan for n instances (host array, copied).  T [n][2] (T_LR, T_RL) and info [n][3]
- * (self-energy, Step 1 and corner codes as in the single calls) are device outputs in the caller's
- * order, written by every execution.  Creation runs the batch once (the outputs then already hold a
+/* Build a plan for n instances (host array, copied).  T [n][2] (T_LR, T_RL) and info [n][4]
+ * (self-energy, Step 1 and corner codes as in the single calls, then the decimation passes used) are
+ * device outputs in the caller's order, written by every execution.  Creation runs the batch once (the outputs then already hold a
  * result) and waits for it.  The plan runs on ctx's device and is ordered with ctx's stream. */
 ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_plan_opts *opts, double *T,
                          int *info, ss_plan **plan);

@@ -42,7 +42,7 @@ struct Group {
   void *work = nullptr;    // Q, sigma, inj, gc, T, info of one chunk
   ss_c128 *Q = nullptr, *sigma = nullptr, *inj = nullptr, *gc = nullptr;
   double *T = nullptr;
-  int *info = nullptr;  // [3][chunk]
+  int *info = nullptr;  // [4][chunk]
 };
 
 __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig, int count, int cap, double *T,
@@ -52,7 +52,7 @@ __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig,
   const int o = orig[j];
   T[2 * o] = Tc[2 * j];
   T[2 * o + 1] = Tc[2 * j + 1];
-  for (int k = 0; k < 3; ++k) info[3 * o + k] = ic[k * cap + j];
+  for (int k = 0; k < 4; ++k) info[4 * o + k] = ic[k * cap + j];
 }
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
@@ -170,7 +170,7 @@ ss_status build_chunks(ss_plan *p, Group &g, int chunk) {
   const size_t bQ = align256(sizeof(ss_c128) * qmax * 2 * ss2), bS = align256(sizeof(ss_c128) * chunk * 2 * ss2),
                bI = align256(sizeof(ss_c128) * chunk * 2 * (size_t)g.s * std::max(m, 1)),
                bG = align256(sizeof(ss_c128) * chunk * 4 * ss2), bT = align256(sizeof(double) * 2 * chunk),
-               bN = align256(sizeof(int) * 3 * chunk);
+               bN = align256(sizeof(int) * 4 * chunk);
   if (g.work) (void)hipFree(g.work);
   g.work = nullptr;
   if (hipMalloc(&g.work, bQ + bS + bI + bG + bT + bN) != hipSuccess) {
@@ -192,9 +192,9 @@ ss_status build_chunks(ss_plan *p, Group &g, int chunk) {
 ss_status run_chunk(ss_plan *p, Group &g, const Chunk &c) {
   ss_ctx *x = g.ctx;
   const int C = c.count, s = g.s, m = p->opts.m;
-  int *i_sig = g.info, *i_pre = g.info + g.chunk, *i_obc = g.info + 2 * g.chunk;
+  int *i_sig = g.info, *i_pre = g.info + g.chunk, *i_obc = g.info + 2 * g.chunk, *i_it = g.info + 3 * g.chunk;
   SS_TRY(lead_selfenergy(x, C, s, C, nullptr, nullptr, nullptr, nullptr, nullptr, c.rb.E, p->opts.eta,
-                         p->opts.sigma_tol, p->opts.sigma_passes, g.sigma, nullptr, nullptr, i_sig, c.lead_tab));
+                         p->opts.sigma_tol, p->opts.sigma_passes, g.sigma, i_it, nullptr, i_sig, c.lead_tab));
   SS_TRY(precompute_ragged(x, c.rb, SS_PREC_FP64, g.Q, i_pre));
   const int mm = c.any_psi ? m : 0;
   if (mm > 0) SS_TRY(injection_left(x, C, s, g.sigma, 0.0, mm, g.inj, nullptr));

@@ -371,7 +371,8 @@ class Instance:
 class Plan:
     """ss_plan over a list of Instance objects; keeps every tensor it was built from alive.
 
-    T [n][2] float64 and info [n][3] int32 (device) are written by every ``execute()``.
+    T [n][2] float64 and info [n][4] int32 (device: self-energy, Step 1 and corner codes, decimation
+    passes) are written by every ``execute()``.
     """
 
     def __init__(self, ctx: Context, instances, eta: float, m: int = 0, use_graph: bool = True,
@@ -403,7 +404,7 @@ class Plan:
         self.ctx = ctx
         self.instances = list(instances)
         self.T = torch.zeros(n, 2, dtype=torch.float64, device=dev)
-        self.info = torch.zeros(n, 3, dtype=torch.int32, device=dev)
+        self.info = torch.zeros(n, 4, dtype=torch.int32, device=dev)
         h = ctypes.c_void_p()
         ctx.check(ctx.lib.ss_plan_create(ctx.handle, n, arr, ctypes.byref(opts), _ptr(self.T), _ptr(self.info),
                                          ctypes.byref(h)))
