@@ -245,7 +245,7 @@ ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, i
                            double *tune_ms);
 /* Nodes of the captured graph (0 without use_graph). */
 long long ss_plan_graph_nodes(const ss_plan *plan);
-/* Waits for the plan's work and frees it. */
+/* Waits for the plan's work and frees it (it does not use the context: a plan may outlive it). */
 void ss_plan_destroy(ss_plan *plan);
 
 #ifdef __cplusplus

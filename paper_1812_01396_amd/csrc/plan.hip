@@ -60,7 +60,8 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 }  // namespace
 
 struct ss_plan {
-  ss_ctx *ctx = nullptr;  // caller's context: device and launch stream
+  ss_ctx *ctx = nullptr;  // caller's context: device and launch stream (not touched by ss_plan_destroy)
+  int device = 0;
   int n = 0;
   std::vector<ss_instance> inst;
   ss_plan_opts opts{};
@@ -273,6 +274,7 @@ ss_status autotune(ss_plan *p, Group &g, int chunk_max) {
 }
 
 void release(ss_plan *p) {
+  if (p->origin) (void)hipStreamSynchronize(p->origin);
   if (p->exec) (void)hipGraphExecDestroy(p->exec);
   if (p->graph) (void)hipGraphDestroy(p->graph);
   for (Group &g : p->groups) {
@@ -285,10 +287,7 @@ void release(ss_plan *p) {
   }
   if (p->start) (void)hipEventDestroy(p->start);
   if (p->finish) (void)hipEventDestroy(p->finish);
-  if (p->origin) {
-    (void)hipStreamSynchronize(p->origin);
-    (void)hipStreamDestroy(p->origin);
-  }
+  if (p->origin) (void)hipStreamDestroy(p->origin);
   delete p;
 }
 
@@ -317,6 +316,7 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
   ss_plan *p = new (std::nothrow) ss_plan();
   if (!p) return fail(ctx, SS_ERR_NOMEM, "ss_plan_create: out of host memory");
   p->ctx = ctx;
+  p->device = ctx->device;
   p->n = n;
   p->inst.assign(inst, inst + n);
   p->opts = *opts;
@@ -428,9 +428,8 @@ long long ss_plan_graph_nodes(const ss_plan *p) { return p ? (long long)p->graph
 
 void ss_plan_destroy(ss_plan *p) {
   if (!p) return;
-  (void)hipSetDevice(p->ctx->device);
-  (void)hipStreamSynchronize(p->ctx->stream);
-  release(p);
+  (void)hipSetDevice(p->device);
+  release(p);  // waits for the plan's own streams
 }
 
 }  // extern "C"

@@ -6,9 +6,9 @@
 // Used for the recursion products of the mixed-precision path; the LU, the corner system and all
 // residuals stay FP64.
 //
-// Register layout of v_mfma_f32_16x16x4_f32 (wave64): A (16x4): lane l holds A[l % 16][l / 16];
-// B (4x16): lane l holds B[l / 16][l % 16]; D (16x16): lane l, element j holds D[4*j + l / 16][l % 16]
-// (the same arrangement as the FP64 instruction).
+// Register layout of v_mfma_f32_16x16x4_f32 (wave64), measured: A (16x4): lane l holds A[l % 16][l / 16];
+// B (4x16): lane l holds B[l / 16][l % 16]; D (16x16): lane l, element j holds D[4*(l / 16) + j][l % 16]
+// (the inputs are arranged as for the FP64 instruction, the output rows are not).
 #pragma once
 
 #include "tile.hpp"
@@ -147,7 +147,7 @@ __device__ __forceinline__ void acc_foreach32(const Acc32<T> &acc, F &&f) {
     for (int j = 0; j < T::FN; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int r = wm * T::FM * 16 + i * 16 + 4 * q + (lane >> 4);
+        const int r = wm * T::FM * 16 + i * 16 + 4 * (lane >> 4) + q;
         const int c = wn * T::FN * 16 + j * 16 + (lane & 15);
         f(r, c, make_double2((double)acc.re[i][j][q], (double)acc.im[i][j][q]));
       }

@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import torch
 
@@ -163,8 +164,11 @@ class Context:
         if st != SS_OK:
             raise SplitSolveError(st, "ss_create failed")
         self.handle = h
+        self._plans = weakref.WeakSet()  # plans built on this context are closed before it
 
     def close(self):
+        for p in list(getattr(self, "_plans", ())):
+            p.close()
         if getattr(self, "handle", None):
             self.lib.ss_destroy(self.handle)
             self.handle = None
@@ -409,6 +413,7 @@ class Plan:
         ctx.check(ctx.lib.ss_plan_create(ctx.handle, n, arr, ctypes.byref(opts), _ptr(self.T), _ptr(self.info),
                                          ctypes.byref(h)))
         self.handle = h
+        ctx._plans.add(self)
 
     def execute(self):
         self.ctx.check(self.ctx.lib.ss_plan_execute(self.handle))

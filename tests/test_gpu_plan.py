@@ -58,8 +58,15 @@ def _make(ss, insts, Es, m):
 
 
 def _tolerance(inst, E):
+    """max(1e-10, 10 u kappa_dec, 10 x the spread of the oracle's two elimination orders for Q).
+
+    Alg. 1 pivots only inside blocks: a recursion whose pivot blocks D_i are ill-conditioned loses
+    digits even when A is well-conditioned, and two exact routes of the oracle then differ by as much."""
     a0, a1, am1 = selfenergy.lead_blocks(inst.H00, inst.H01, inst.S00, inst.S01, E, ETA)
-    return max(TOL, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1))
+    ad, au, al = transport.device_blocks(inst.Hd, inst.Hu, inst.Sd, inst.Su, E)
+    q = transport.first_last_columns(ad, au, al)
+    spread = _rel(transport.first_last_columns_mirrored(ad, au, al), q)
+    return max(TOL, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1), 10 * spread)
 
 
 def _gamma_factor(inst, E):
