@@ -387,7 +387,7 @@ def main():
         pipe.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    k_ms, k_launches = timed_ctx.kernel_timer_read()
+    k_ms, k_launches, k_flops = timed_ctx.kernel_timer_read(with_flops=True)
     timed_ctx.kernel_timer(None)
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
@@ -406,6 +406,7 @@ def main():
         "dec_update": args.steps * 32.0 * s**3 * float(it_np.sum()),
         "form": args.steps * nbatch * 2 * (nb - 1) * 8.0 * s**3,
         "chain": args.steps * nbatch * 2 * (nb - 1) * 8.0 * s**3,
+        "lu_gemm": k_flops,  # stated per launch by the library (8 m n k per complex product)
     }
     roof = None
     if k_launches > 0 and fam in fam_flops:

@@ -80,13 +80,15 @@ size_t ss_workspace_bytes(const ss_ctx *ctx);
 /* Kernel timing probe (a profiling aid).  ss_kernel_timer(ctx, family) waits for the stream, clears
  * the accumulated time and from then on brackets every launch of that kernel family on this context
  * with a pair of HIP events on the context's stream (NULL or "" switches the probe off).
- * ss_kernel_timer_read waits for the stream and returns the summed event time in milliseconds and
- * the number of timed launches since the last read, then clears them.  Families: "form" (diagonal
- * block formation and product of the recursion), "chain" (Q_i = -X_i Q_{i-1}), "panel",
- * "panel_update", "row_block", "back_sub" (LU and triangular solves), "dec_update" (decimation pass
+ * ss_kernel_timer_read waits for the stream and returns the summed event time in milliseconds, the
+ * number of timed launches and (flops, may be NULL) the algorithmic flops of those launches where the
+ * launch site states them (8 m n k per complex product; "lu_gemm" only, else 0) since the last read,
+ * then clears them.  Families: "form" (diagonal block formation and product of the recursion),
+ * "chain" (Q_i = -X_i Q_{i-1}), "panel" (LU panel factorization), "lu_gemm" (LU trailing and
+ * triangular-solve products), "trsm" (triangular-solve leaves), "dec_update" (decimation pass
  * products), "obc" (corner system and psi products), "trans" (transmission). */
 ss_status ss_kernel_timer(ss_ctx *ctx, const char *family);
-ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches);
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops);
 
 /* ---------------------------------------------------------------- inputs */
 

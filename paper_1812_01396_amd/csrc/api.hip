@@ -63,10 +63,13 @@ static hipEvent_t timer_event(ss_ctx *ctx) {
   return ctx->timer_events[ctx->timer_used++];
 }
 
-KernelScope::KernelScope(ss_ctx *c, const char *family) : ctx(c), on(false) {
+KernelScope::KernelScope(ss_ctx *c, const char *family, double flops) : ctx(c), on(false) {
   if (!ctx->timer_family.empty() && ctx->timer_family == family) {
     hipEvent_t e = timer_event(ctx);
-    if (e && hipEventRecord(e, ctx->stream) == hipSuccess) on = true;
+    if (e && hipEventRecord(e, ctx->stream) == hipSuccess) {
+      on = true;
+      ctx->timer_flops += flops;
+    }
   }
 }
 
@@ -158,10 +161,11 @@ ss_status ss_kernel_timer(ss_ctx *ctx, const char *family) {
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
   ctx->timer_family = family ? family : "";
   ctx->timer_used = 0;
+  ctx->timer_flops = 0.0;
   return SS_OK;
 }
 
-ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches) {
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops) {
   SS_TRY(enter(ctx));
   if (!total_ms || !launches) return fail(ctx, SS_ERR_ARG, "ss_kernel_timer_read: null output");
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
@@ -175,7 +179,9 @@ ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launche
   }
   *total_ms = t;
   *launches = (long long)pairs;
+  if (flops) *flops = ctx->timer_flops;
   ctx->timer_used = 0;
+  ctx->timer_flops = 0.0;
   return SS_OK;
 }
 

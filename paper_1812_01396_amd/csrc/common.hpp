@@ -85,6 +85,7 @@ struct ss_ctx {
   std::string timer_family;
   std::vector<hipEvent_t> timer_events;
   size_t timer_used = 0;
+  double timer_flops = 0.0;  // algorithmic flops of the timed launches (where the launch site states them)
 };
 
 namespace ss {
@@ -99,7 +100,7 @@ ss_status host_word(ss_ctx *ctx, int **out);
 struct KernelScope {
   ss_ctx *ctx;
   bool on;
-  KernelScope(ss_ctx *c, const char *family);
+  KernelScope(ss_ctx *c, const char *family, double flops = 0.0);
   ~KernelScope();
 };
 
