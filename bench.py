@@ -149,18 +149,27 @@ class UnevenPipeline:
         dev = torch.device("cuda", 0)
         self.ctx = ss.Context(0)
         self.instances = []
-        for spec in self.specs:
+        t0 = time.perf_counter()
+        for i, spec in enumerate(self.specs):
+            if i % 32 == 0:
+                print(f"uneven256: building instance {i} of {len(self.specs)} ({time.perf_counter() - t0:.0f} s)",
+                      file=sys.stderr, flush=True)
             s, nb, E, k, _ = spec
             h00, h01, s00, s01 = (torch.as_tensor(a).to(dev) for a in uneven_cell(spec))
             x = ss.Instance(h00.expand(nb, s, s).contiguous(), h01.expand(nb - 1, s, s).contiguous(),
                             s00.expand(nb, s, s).contiguous(), s01.expand(nb - 1, s, s).contiguous(),
                             h00, h01, s00, s01, E, torch.zeros(nb, s, m, dtype=torch.complex128, device=dev))
             self.instances.append(x)
+        torch.cuda.synchronize()
+        print(f"uneven256: inputs resident ({time.perf_counter() - t0:.0f} s); creating the plan", file=sys.stderr,
+              flush=True)
         t0 = time.perf_counter()
         self.plan = ss.Plan(self.ctx, self.instances, self.w["eta"], m=m, use_graph=use_graph, autotune=autotune,
                             mem_bytes=int(mem_gib * (1 << 30)))
         torch.cuda.synchronize()
         self.create_s = time.perf_counter() - t0
+        print(f"uneven256: plan created in {self.create_s:.1f} s, graph nodes {self.plan.graph_nodes}", file=sys.stderr,
+              flush=True)
 
     def run(self):
         self.plan.execute()
@@ -173,11 +182,13 @@ def run_uneven(args):
     for _ in range(args.warmup):
         pipe.run()
     torch.cuda.synchronize()
+    print("uneven256: warmup done", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         pipe.run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    print(f"uneven256: {args.steps} steps in {elapsed:.2f} s", file=sys.stderr, flush=True)
     T = pipe.plan.T.cpu().numpy()
     info = pipe.plan.info.cpu().numpy()
     m = pipe.w["m"]

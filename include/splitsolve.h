@@ -197,6 +197,55 @@ ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kid
 ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi,
                               const ss_c128 *sigma, double *T);
 
+/* ---------------------------------------------------------------- learned warm start
+ * The decimation takes no starting iterate; Newton's method on the fixed-point equation of the
+ * self-energy does.  For the right lead (the left swaps a1 and am1), with g = (a0 - Sigma)^{-1},
+ * M = a1 g, N = g am1 and F = Sigma - a1 N, a Newton step solves the Stein equation D - M D N = -F by
+ * Smith's doubling (D += M_j D N_j, M_{j+1} = M_j^2, N_{j+1} = N_j^2, rebalanced) and sets
+ * Sigma += D.  The starting iterate comes from a multilayer perceptron trained on self-energies of the
+ * decimation.  (Newton on the quadratic and the Stein equation are not in the paper; the self-energies
+ * are those of Sec. 3A.) */
+
+/* Parameters of a perceptron with layer sizes dims[0..nlayer] (host array): per layer
+ * W [dims[l]][dims[l+1]] row-major, then b [dims[l+1]], FP32.  0 for invalid sizes. */
+size_t ss_mlp_param_count(int nlayer, const int *dims);
+/* Forward pass on n rows X [n][dims[0]] (FP32, device).  acts (device, FP32) receives every layer's
+ * output in order, [n][dims[1]], ..., [n][dims[nlayer]] (hidden layers tanh, the last linear); the
+ * network output is the last block.  Products run on the FP32 matrix cores with FP32 accumulation. */
+ss_status ss_mlp_forward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                         float *acts);
+/* Gradients (same packing as params) of L = sum (Y - target)^2 / (n dims[nlayer]) by back-propagation
+ * through the acts of the forward pass of the same params and X; loss (device double) receives L. */
+ss_status ss_mlp_backward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                          const float *acts, const float *target, float *grads, double *loss);
+/* One Adam step (step = 1, 2, ...) on count parameters with moment buffers m, v (device, FP32). */
+ss_status ss_mlp_adam(ss_ctx *ctx, size_t count, float *params, const float *grads, float *m, float *v, float lr,
+                      float beta1, float beta2, float eps, int step);
+/* Features of (E, k) (device doubles [n]): X [n][3 + 4 nfreq] = [E/e_scale, cos k, sin k,
+ * sin(j pi E/e_scale), cos(j pi E/e_scale) (j = 1..nfreq), cos(j k), sin(j k) (j = 2..nfreq+1)]. */
+ss_status ss_warm_features(ss_ctx *ctx, int n, const double *E, const double *k, int nfreq, double e_scale, float *X);
+/* Per component of the encoding [Re Sigma_L, Im Sigma_L, Re Sigma_R, Im Sigma_R] (4 s^2 values) of
+ * sigma [n][2][s][s]: mean and standard deviation over the n instances (std at least std_floor). */
+ss_status ss_sigma_moments(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, float std_floor, float *mean, float *std);
+/* y [n][4 s^2] = (encoding - mean) / std, and back: sigma = mean + std * y. */
+ss_status ss_sigma_encode(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, const float *mean, const float *std,
+                          float *y);
+ss_status ss_sigma_decode(ss_ctx *ctx, int n, int s, const float *y, const float *mean, const float *std,
+                          ss_c128 *sigma);
+/* Self-energies as ss_lead_selfenergy, starting Newton from sigma_init [batch][2][s][s] (L, R; must not
+ * alias sigma).  A side is accepted when its relative residual ||F||_F / ||Sigma||_F <= tol (<= 0:
+ * 1e-10) within max_newton steps (<= 0: 8; Smith's doubling with at most smith_steps doublings, <= 0:
+ * 40) and its propagator has spectral radius <= 1 + 1e-8 (the retarded root), estimated from 40
+ * normalised squarings.  Instances with a rejected side are recomputed by the decimation (tol 1e-14,
+ * at most 200 passes).  Outputs (device, any may be NULL except sigma): newton_iters [batch] (largest
+ * of the two sides), dec_iters [batch] (decimation passes of the fallback, 0 if accepted), resid
+ * [batch][2] (last Newton residuals, L then R), info [batch]: 0 accepted, -2 fallback used, else the
+ * decimation's code.  Waits for the stream (host polls); not usable in sync-free mode. */
+ss_status ss_lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
+                                  const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
+                                  double eta, const ss_c128 *sigma_init, double tol, int max_newton, int smith_steps,
+                                  ss_c128 *sigma, int *newton_iters, int *dec_iters, double *resid, int *info);
+
 /* ---------------------------------------------------------------- uneven batches
  * Many independent (E, k) instances of different block size s and block count nb (the paper solves
  * energy points independently side by side, Sec. 4).  A plan groups the instances by s, sorts each
@@ -245,7 +294,9 @@ ss_status ss_plan_execute(ss_plan *plan);
 int ss_plan_groups(const ss_plan *plan);
 ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, int *chunk, int *lu_width,
                            double *tune_ms);
-/* Nodes of the captured graph (0 without use_graph). */
+/* Nodes of the captured graph (0 without use_graph); a negative value -n means a graph of n nodes was
+ * captured but judged too large to instantiate (over 200000 nodes), and the plan runs as one
+ * sync-free enqueue of the same launches instead. */
 long long ss_plan_graph_nodes(const ss_plan *plan);
 /* Waits for the plan's work and frees it (it does not use the context: a plan may outlive it). */
 void ss_plan_destroy(ss_plan *plan);

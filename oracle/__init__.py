@@ -16,8 +16,11 @@ Contents (each function cites the passage of the paper it follows):
   (Sec. 3B, Step 1), G^R corner blocks and psi from a direct solve of T = A - Sigma (Sec. 2B,
   Eq. (negf)/(wf)), the SMW quantities R, z (Sec. 3B, Eq. (x)) and the Caroli transmission.
 * ``bands``: open-channel count from the lead band structure (independent physics pin).
+* ``warmstart``: Newton's method on the self-energy's fixed-point equation with the Stein correction by
+  the Kronecker system or Smith's doubling, and the float64 forward/backward passes and Adam update of
+  the multilayer perceptron that predicts the starting iterate.
 
 Parity is pinned for every function here by the ``-m "not gpu"`` tests (closed forms, brute force,
 invariants, band counting).  No function is "parity unpinned".
 """
-from . import bands, linalg, selfenergy, transport  # noqa: F401
+from . import bands, linalg, selfenergy, transport, warmstart  # noqa: F401

@@ -8,6 +8,7 @@ Caroli transmission.  See include/splitsolve.h for the ABI.
 from .splitsolve import (  # noqa: F401
     Context,
     Instance,
+    MLP,
     Plan,
     SplitSolveError,
     load_library,
@@ -16,6 +17,11 @@ from .splitsolve import (  # noqa: F401
     ss_apply_obc,
     ss_injection_left,
     ss_lead_selfenergy,
+    ss_lead_selfenergy_warm,
+    ss_sigma_decode,
+    ss_sigma_encode,
+    ss_sigma_moments,
+    ss_warm_features,
     ss_precompute_columns,
     ss_refine_psi,
     ss_transmission,

@@ -276,4 +276,98 @@ ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, cons
   return transmission_psi(ctx, batch, nb, s, m, psi, sigma, T);
 }
 
+// ---------------------------------------------------------------- learned warm start
+
+static bool dims_ok(int nlayer, const int *dims) {
+  if (nlayer < 1 || nlayer > 16 || !dims) return false;
+  for (int l = 0; l <= nlayer; ++l)
+    if (dims[l] < 1) return false;
+  return true;
+}
+
+size_t ss_mlp_param_count(int nlayer, const int *dims) {
+  return dims_ok(nlayer, dims) ? mlp_param_count(nlayer, dims) : 0;
+}
+
+ss_status ss_mlp_forward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                         float *acts) {
+  SS_TRY(enter(ctx));
+  if (!dims_ok(nlayer, dims) || n < 0) return fail(ctx, SS_ERR_ARG, "ss_mlp_forward: bad layer sizes");
+  if (n == 0) return SS_OK;
+  if (!params || !X || !acts) return fail(ctx, SS_ERR_ARG, "ss_mlp_forward: null pointer");
+  if (n > 65535 * 64) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_mlp_forward: n too large");
+  return mlp_forward(ctx, nlayer, dims, params, n, X, acts);
+}
+
+ss_status ss_mlp_backward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                          const float *acts, const float *target, float *grads, double *loss) {
+  SS_TRY(enter(ctx));
+  if (!dims_ok(nlayer, dims) || n < 1) return fail(ctx, SS_ERR_ARG, "ss_mlp_backward: bad sizes");
+  if (!params || !X || !acts || !target || !grads || !loss)
+    return fail(ctx, SS_ERR_ARG, "ss_mlp_backward: null pointer");
+  if (n > 65535 * 64) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_mlp_backward: n too large");
+  return mlp_backward(ctx, nlayer, dims, params, n, X, acts, target, grads, loss);
+}
+
+ss_status ss_mlp_adam(ss_ctx *ctx, size_t count, float *params, const float *grads, float *m, float *v, float lr,
+                      float beta1, float beta2, float eps, int step) {
+  SS_TRY(enter(ctx));
+  if (step < 1 || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(ctx, SS_ERR_ARG, "ss_mlp_adam: bad hyper-parameters");
+  if (count == 0) return SS_OK;
+  if (!params || !grads || !m || !v) return fail(ctx, SS_ERR_ARG, "ss_mlp_adam: null pointer");
+  return mlp_adam(ctx, count, params, grads, m, v, lr, beta1, beta2, eps, step);
+}
+
+ss_status ss_warm_features(ss_ctx *ctx, int n, const double *E, const double *k, int nfreq, double e_scale, float *X) {
+  SS_TRY(enter(ctx));
+  if (n < 0 || nfreq < 0 || nfreq > 64 || !(e_scale > 0)) return fail(ctx, SS_ERR_ARG, "ss_warm_features: bad sizes");
+  if (n == 0) return SS_OK;
+  if (!E || !k || !X) return fail(ctx, SS_ERR_ARG, "ss_warm_features: null pointer");
+  return warm_features(ctx, n, E, k, nfreq, e_scale, X);
+}
+
+ss_status ss_sigma_moments(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, float std_floor, float *mean, float *std) {
+  SS_TRY(enter(ctx));
+  if (n < 1 || s < 1 || s > SS_MAX_S) return fail(ctx, SS_ERR_ARG, "ss_sigma_moments: bad sizes");
+  if (!sigma || !mean || !std) return fail(ctx, SS_ERR_ARG, "ss_sigma_moments: null pointer");
+  return sigma_moments(ctx, n, s, sigma, std_floor, mean, std);
+}
+
+ss_status ss_sigma_encode(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, const float *mean, const float *std,
+                          float *y) {
+  SS_TRY(enter(ctx));
+  if (n < 0 || s < 1 || s > SS_MAX_S) return fail(ctx, SS_ERR_ARG, "ss_sigma_encode: bad sizes");
+  if (n == 0) return SS_OK;
+  if (!sigma || !mean || !std || !y) return fail(ctx, SS_ERR_ARG, "ss_sigma_encode: null pointer");
+  return sigma_encode(ctx, n, s, sigma, mean, std, y);
+}
+
+ss_status ss_sigma_decode(ss_ctx *ctx, int n, int s, const float *y, const float *mean, const float *std,
+                          ss_c128 *sigma) {
+  SS_TRY(enter(ctx));
+  if (n < 0 || s < 1 || s > SS_MAX_S) return fail(ctx, SS_ERR_ARG, "ss_sigma_decode: bad sizes");
+  if (n == 0) return SS_OK;
+  if (!sigma || !mean || !std || !y) return fail(ctx, SS_ERR_ARG, "ss_sigma_decode: null pointer");
+  return sigma_decode(ctx, n, s, y, mean, std, sigma);
+}
+
+ss_status ss_lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
+                                  const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
+                                  double eta, const ss_c128 *sigma_init, double tol, int max_newton, int smith_steps,
+                                  ss_c128 *sigma, int *newton_iters, int *dec_iters, double *resid, int *info) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || s < 1 || nk < 1 || max_newton < 0 || smith_steps < 0)
+    return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy_warm: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_lead_selfenergy_warm: s > SS_MAX_S");
+  if (batch > 32767) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_lead_selfenergy_warm: batch > 32767");
+  if (batch == 0) return SS_OK;
+  if (!H00 || !H01 || !S00 || !S01 || !E || !sigma_init || !sigma)
+    return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy_warm: null pointer");
+  if (sigma_init == sigma) return fail(ctx, SS_ERR_ARG, "ss_lead_selfenergy_warm: sigma_init must not alias sigma");
+  if (ctx->sync_free) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_lead_selfenergy_warm: needs host polls");
+  return lead_selfenergy_warm(ctx, batch, s, nk, H00, H01, S00, S01, kidx, E, eta, sigma_init, tol, max_newton,
+                              smith_steps, sigma, newton_iters, dec_iters, resid, info);
+}
+
 }  // extern "C"

@@ -63,6 +63,10 @@ enum Slot {
   kSlotFact,       // kept factorizations of the first-column recursion (for refinement)
   kSlotFactPerm,
   kSlotRef,        // refinement work
+  kSlotWarm,       // Newton work of the warm-started self-energies
+  kSlotWarmMisc,
+  kSlotMlp,        // split-K partial products of the network
+  kSlotMlpDz,      // back-propagated gradients
   kNumSlots
 };
 

@@ -46,6 +46,25 @@ ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, 
                      const ss_c128 *sigma, int m, const ss_c128 *inj, ss_c128 *psi, double tol, int max_iter,
                      int *iters, double *resid);
 
+ss_status lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
+                               const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E, double eta,
+                               const ss_c128 *sigma_init, double tol, int max_newton, int smith_steps,
+                               ss_c128 *sigma, int *newton_iters, int *dec_iters, double *resid, int *info);
+
+ss_status sgemm(ss_ctx *ctx, bool ta, bool tb, int epi, const float *A, int lda, const float *B, int ldb, float *C,
+                int ldc, int M, int N, int K, const float *bias, const float *aux, int ldaux);
+size_t mlp_param_count(int nlayer, const int *dims);
+ss_status mlp_forward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                      float *acts);
+ss_status mlp_backward(ss_ctx *ctx, int nlayer, const int *dims, const float *params, int n, const float *X,
+                       const float *acts, const float *target, float *grads, double *loss);
+ss_status mlp_adam(ss_ctx *ctx, size_t count, float *params, const float *grads, float *m, float *v, float lr,
+                   float b1, float b2, float eps, int step);
+ss_status warm_features(ss_ctx *ctx, int n, const double *E, const double *k, int nfreq, double e_scale, float *X);
+ss_status sigma_moments(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, float std_floor, float *mean, float *std);
+ss_status sigma_encode(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, const float *mean, const float *std, float *y);
+ss_status sigma_decode(ss_ctx *ctx, int n, int s, const float *y, const float *mean, const float *std, ss_c128 *sigma);
+
 ss_status transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
                            double *T);
 

@@ -57,6 +57,9 @@ __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig,
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
+// largest captured graph that is instantiated; larger plans run as a sync-free enqueue
+constexpr size_t kMaxGraphNodes = 200000;
+
 }  // namespace
 
 struct ss_plan {
@@ -73,6 +76,7 @@ struct ss_plan {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   size_t graph_nodes = 0;
+  long long graph_refused = 0;  // nodes of a captured graph judged too large to instantiate
 };
 
 namespace {
@@ -346,16 +350,31 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
     std::stable_sort(g.order.begin(), g.order.end(), [&](int a, int b) { return inst[a].nb > inst[b].nb; });
     p->groups.push_back(g);
   }
+  // memory budget per group: a floor that lets a small group run whole (or at least half of an even
+  // split of the budget), and the rest of the budget in proportion to the group's work (nb s^3)
+  const int ngroups = (int)p->groups.size();
+  std::vector<size_t> floor_b(ngroups), gbytes(ngroups, 0), gwork(ngroups, 0);
+  size_t floors = 0;
+  for (int gi = 0; gi < ngroups; ++gi) {
+    const Group &g = p->groups[gi];
+    for (int i : g.order) {
+      gbytes[gi] += instance_bytes(g.s, inst[i].nb, p->opts.m);
+      gwork[gi] += (size_t)inst[i].nb * g.s * g.s * g.s / 64 + 1;
+    }
+    floor_b[gi] = std::min(gbytes[gi], p->opts.mem_bytes / (2 * (size_t)ngroups));
+    floors += floor_b[gi];
+  }
+  const size_t rest = p->opts.mem_bytes > floors ? p->opts.mem_bytes - floors : 0;
+  int gi = 0;
   for (Group &g : p->groups) {
+    const size_t share = floor_b[gi] + (size_t)((double)rest * gwork[gi] / work_total);
+    ++gi;
     if (hipStreamCreateWithFlags(&g.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&g.done, hipEventDisableTiming) != hipSuccess)
       return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: stream creation failed"));
     if (ss_create(&g.ctx, ctx->device, g.stream) != SS_OK)
       return bail(fail(ctx, SS_ERR_NOMEM, "ss_plan_create: group context"));
-    // memory share of the group in proportion to its work; the chunk must hold its largest instance
-    size_t work = 0;
-    for (int i : g.order) work += (size_t)inst[i].nb * g.s * g.s * g.s / 64 + 1;
-    const size_t share = (size_t)((double)p->opts.mem_bytes * work / work_total);
+    // the chunk must hold at least the group's largest instance
     int chunk = 0;
     size_t used = 0;
     for (int i : g.order) {
@@ -382,10 +401,20 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
     p->graph = graph;
     if (st != SS_OK) return bail(st);
     if (ec != hipSuccess || !graph) return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: capture failed"));
-    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-      return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed"));
     size_t nodes = 0;
-    if (hipGraphGetNodes(p->graph, nullptr, &nodes) == hipSuccess) p->graph_nodes = nodes;
+    if (hipGraphGetNodes(p->graph, nullptr, &nodes) != hipSuccess)
+      return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: graph node count failed"));
+    if (nodes > kMaxGraphNodes) {
+      // too large to instantiate as one graph: the plan runs as one sync-free enqueue instead
+      (void)hipGraphDestroy(p->graph);
+      p->graph = nullptr;
+      p->graph_nodes = 0;
+      p->graph_refused = (long long)nodes;
+    } else {
+      if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed"));
+      p->graph_nodes = nodes;
+    }
   }
   *out = p;
   return SS_OK;
@@ -424,7 +453,10 @@ ss_status ss_plan_describe(const ss_plan *p, int group, int *s, int *count, int 
 
 int ss_plan_groups(const ss_plan *p) { return p ? (int)p->groups.size() : 0; }
 
-long long ss_plan_graph_nodes(const ss_plan *p) { return p ? (long long)p->graph_nodes : 0; }
+long long ss_plan_graph_nodes(const ss_plan *p) {
+  if (!p) return 0;
+  return p->graph_nodes ? (long long)p->graph_nodes : -p->graph_refused;
+}
 
 void ss_plan_destroy(ss_plan *p) {
   if (!p) return;

@@ -26,7 +26,9 @@ EXPORTS = (
     "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
-    "ss_plan_graph_nodes", "ss_plan_destroy",
+    "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
+    "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
+    "ss_lead_selfenergy_warm",
 )
 
 
@@ -123,6 +125,26 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_plan_graph_nodes.restype = ctypes.c_longlong
     lib.ss_plan_destroy.argtypes = [P]
     lib.ss_plan_destroy.restype = None
+    IP = ctypes.POINTER(ctypes.c_int)
+    F = ctypes.c_float
+    lib.ss_mlp_param_count.argtypes = [I, IP]
+    lib.ss_mlp_param_count.restype = Z
+    lib.ss_mlp_forward.argtypes = [P, I, IP, P, I, P, P]
+    lib.ss_mlp_forward.restype = I
+    lib.ss_mlp_backward.argtypes = [P, I, IP, P, I, P, P, P, P, P]
+    lib.ss_mlp_backward.restype = I
+    lib.ss_mlp_adam.argtypes = [P, Z, P, P, P, P, F, F, F, F, I]
+    lib.ss_mlp_adam.restype = I
+    lib.ss_warm_features.argtypes = [P, I, P, P, I, D, P]
+    lib.ss_warm_features.restype = I
+    lib.ss_sigma_moments.argtypes = [P, I, I, P, F, P, P]
+    lib.ss_sigma_moments.restype = I
+    lib.ss_sigma_encode.argtypes = [P, I, I, P, P, P, P]
+    lib.ss_sigma_encode.restype = I
+    lib.ss_sigma_decode.argtypes = [P, I, I, P, P, P, P]
+    lib.ss_sigma_decode.restype = I
+    lib.ss_lead_selfenergy_warm.argtypes = [P, I, I, I, P, P, P, P, P, P, D, P, D, I, I, P, P, P, P, P]
+    lib.ss_lead_selfenergy_warm.restype = I
     _lib = lib
     return lib
 
@@ -444,3 +466,128 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------- learned warm start
+
+
+def _dims_arg(dims):
+    arr = (ctypes.c_int * len(dims))(*[int(d) for d in dims])
+    return len(dims) - 1, arr
+
+
+class MLP:
+    """FP32 perceptron on the GPU (tanh hidden layers, linear output) trained with the library's kernels.
+
+    ``params`` packs W_l [dims[l]][dims[l+1]] then b_l per layer (see ss_mlp_param_count)."""
+
+    def __init__(self, ctx: Context, dims, params=None, seed: int = 0):
+        self.ctx, self.dims = ctx, [int(d) for d in dims]
+        self.nl, self._dims = _dims_arg(self.dims)
+        count = int(ctx.lib.ss_mlp_param_count(self.nl, self._dims))
+        if count == 0:
+            raise ValueError(f"invalid layer sizes {dims}")
+        self.count = count
+        dev = ctx.device
+        if params is None:
+            g = torch.Generator(device="cpu").manual_seed(seed)
+            chunks = []
+            for i in range(self.nl):
+                chunks.append((torch.randn(self.dims[i] * self.dims[i + 1], generator=g, dtype=torch.float64)
+                               / self.dims[i] ** 0.5).float())
+                chunks.append(torch.zeros(self.dims[i + 1], dtype=torch.float32))
+            params = torch.cat(chunks).to(dev)
+        self.params = _need(params, torch.float32, dev, "params", (count,))
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+
+    def acts_size(self, n: int) -> int:
+        return n * sum(self.dims[1:])
+
+    def forward(self, X, acts=None):
+        """Every layer's output in one flat FP32 tensor; returns (acts, output view [n][dims[-1]])."""
+        n = int(X.shape[0])
+        _need(X, torch.float32, self.ctx.device, "X", (n, self.dims[0]))
+        if acts is None:
+            acts = torch.empty(self.acts_size(n), dtype=torch.float32, device=self.ctx.device)
+        self.ctx.check(self.ctx.lib.ss_mlp_forward(self.ctx.handle, self.nl, self._dims, _ptr(self.params), n, _ptr(X),
+                                                   _ptr(acts)))
+        out = acts[n * sum(self.dims[1:-1]):].view(n, self.dims[-1])
+        return acts, out
+
+    def backward(self, X, acts, target):
+        n = int(X.shape[0])
+        _need(target, torch.float32, self.ctx.device, "target", (n, self.dims[-1]))
+        self.ctx.check(self.ctx.lib.ss_mlp_backward(self.ctx.handle, self.nl, self._dims, _ptr(self.params), n, _ptr(X),
+                                                    _ptr(acts), _ptr(target), _ptr(self.grads), _ptr(self.loss)))
+        return self.loss
+
+    def adam(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+        self.step += 1
+        self.ctx.check(self.ctx.lib.ss_mlp_adam(self.ctx.handle, self.count, _ptr(self.params), _ptr(self.grads),
+                                                _ptr(self.m), _ptr(self.v), lr, beta1, beta2, eps, self.step))
+
+
+def ss_warm_features(ctx: Context, E, k, nfreq: int = 8, e_scale: float = 5.0, X=None):
+    n = int(E.numel())
+    _need(E, torch.float64, ctx.device, "E")
+    _need(k, torch.float64, ctx.device, "k", (n,))
+    if X is None:
+        X = torch.empty(n, 3 + 4 * nfreq, dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.lib.ss_warm_features(ctx.handle, n, _ptr(E), _ptr(k), nfreq, e_scale, _ptr(X)))
+    return X
+
+
+def ss_sigma_moments(ctx: Context, sigma, std_floor: float = 0.0):
+    n, _, s, _ = sigma.shape
+    _need(sigma, torch.complex128, ctx.device, "sigma", (n, 2, s, s))
+    mean = torch.empty(4 * s * s, dtype=torch.float32, device=ctx.device)
+    std = torch.empty_like(mean)
+    ctx.check(ctx.lib.ss_sigma_moments(ctx.handle, n, s, _ptr(sigma), std_floor, _ptr(mean), _ptr(std)))
+    return mean, std
+
+
+def ss_sigma_encode(ctx: Context, sigma, mean, std, y=None):
+    n, _, s, _ = sigma.shape
+    _need(sigma, torch.complex128, ctx.device, "sigma", (n, 2, s, s))
+    if y is None:
+        y = torch.empty(n, 4 * s * s, dtype=torch.float32, device=ctx.device)
+    ctx.check(ctx.lib.ss_sigma_encode(ctx.handle, n, s, _ptr(sigma), _ptr(mean), _ptr(std), _ptr(y)))
+    return y
+
+
+def ss_sigma_decode(ctx: Context, y, mean, std, s: int, sigma=None):
+    n = int(y.shape[0])
+    _need(y, torch.float32, ctx.device, "y", (n, 4 * s * s))
+    if sigma is None:
+        sigma = torch.empty(n, 2, s, s, dtype=torch.complex128, device=ctx.device)
+    ctx.check(ctx.lib.ss_sigma_decode(ctx.handle, n, s, _ptr(y), _ptr(mean), _ptr(std), _ptr(sigma)))
+    return sigma
+
+
+def ss_lead_selfenergy_warm(ctx: Context, H00, H01, S00, S01, E, eta: float, sigma_init, kidx=None, tol: float = 0.0,
+                            max_newton: int = 0, smith_steps: int = 0, sigma=None):
+    """Warm-started Sigma (see ss_lead_selfenergy_warm); returns (sigma, newton_iters, dec_iters, resid, info)."""
+    nk, s, _ = H00.shape
+    batch = int(E.numel())
+    dev = ctx.device
+    for nm, t in (("H00", H00), ("H01", H01), ("S00", S00), ("S01", S01)):
+        _need(t, torch.complex128, dev, nm, (nk, s, s))
+    _need(E, torch.float64, dev, "E", (batch,))
+    _need(sigma_init, torch.complex128, dev, "sigma_init", (batch, 2, s, s))
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+        _check_kidx(kidx, nk)
+    if sigma is None:
+        sigma = torch.empty(batch, 2, s, s, dtype=torch.complex128, device=dev)
+    it_n = torch.zeros(batch, dtype=torch.int32, device=dev)
+    it_d = torch.zeros(batch, dtype=torch.int32, device=dev)
+    resid = torch.zeros(batch, 2, dtype=torch.float64, device=dev)
+    info = torch.zeros(batch, dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.ss_lead_selfenergy_warm(ctx.handle, batch, s, nk, _ptr(H00), _ptr(H01), _ptr(S00), _ptr(S01),
+                                              _ptr(kidx), _ptr(E), eta, _ptr(sigma_init), tol, max_newton, smith_steps,
+                                              _ptr(sigma), _ptr(it_n), _ptr(it_d), _ptr(resid), _ptr(info)))
+    return sigma, it_n, it_d, resid, info
