@@ -18,6 +18,10 @@ Workloads (synthetic, seeded; see synth/):
   uneven256  256 instances, each its own lattice-slab crystal: s uniform in {128, 256, 384, 512, 768},
            nb uniform in [16, 64], E uniform in [-5, 5] eV, k uniform in [0, pi); instance i draws from
            numpy default_rng([3, i]); run as one plan (per-size groups, graph replay, autotuned)
+  learned  self-energies of the s = 256 (4x8x8) lead cell, seed 4: a perceptron (35 -> 512 -> 512 -> 512
+           -> 4 s^2, FP32) trained on 10^4 decimation solves (E uniform in [-5, 5] eV, k on a 64-point grid
+           of [0, pi)) and evaluated on 2048 held-out points: cold decimation vs warm start (network +
+           Newton + judge + fallback) vs continuation from the nearest training point
 
 Prints one JSON line.  --gpus > 1 is refused: this build measures one GPU.
 """
@@ -40,7 +44,7 @@ HBM_PEAK_GBS = 8000.0
 
 WORKLOADS = {
     "dft512": dict(s=512, nb=40, n_e=64, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8],
-                   seed=1, eta=1e-8, m=32, chunk=64),
+                   seed=1, eta=1e-8, m=32, chunk=256),
     "chain16": dict(s=16, nb=32, n_e=64, e_lo=-3.0, e_hi=3.0, ks=[0.0], seed=0, eta=1e-8, m=4, chunk=64),
     "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=16),
 }
@@ -137,7 +141,7 @@ class UnevenPipeline:
     """The uneven batch as one ss_plan: crystal devices (every block a copy of the instance's own cell,
     materialised on the GPU), psi for m columns per instance; run() is one plan execution."""
 
-    def __init__(self, n: int = UNEVEN["n"], use_graph: bool = True, autotune: bool = True, mem_gib: float = 32.0):
+    def __init__(self, n: int = UNEVEN["n"], use_graph: bool = True, autotune: bool = True, mem_gib: float = 96.0):
         import torch
 
         import paper_1812_01396_amd as ss
@@ -258,6 +262,139 @@ def run_uneven(args):
     print(json.dumps(out))
 
 
+LEARNED = dict(s=256, seed=4, n_train=10000, n_eval=2048, nk=64, eta=1e-8, width=512, steps=2000, batch=256,
+               lr=1e-3)
+
+
+def run_learned(args):
+    """cfg of the learned warm start: training on the GPU, then cold / warm / continuation solves."""
+    import torch
+
+    import paper_1812_01396_amd as ss
+    import synth
+
+    w = LEARNED
+    s, dev = w["s"], torch.device("cuda", 0)
+    rng = np.random.default_rng(w["seed"])
+    n_all = w["n_train"] + w["n_eval"]
+    E = rng.uniform(-5.0, 5.0, n_all)
+    kgrid = (np.arange(w["nk"]) + 0.5) * np.pi / w["nk"]
+    ki = rng.integers(0, w["nk"], n_all).astype(np.int32)
+    base = synth.DFTLikeCell(synth.SLAB_SHAPES[s], w["seed"])
+    cells = [base.at(k) for k in kgrid]
+    lead = [torch.as_tensor(np.stack([c[j] for c in cells])).to(dev) for j in range(4)]
+    ctx = ss.Context(0)
+    Ed = torch.as_tensor(E).to(dev)
+    kd = torch.as_tensor(kgrid[ki]).to(dev)
+    kid = torch.as_tensor(ki).to(dev)
+    tr, ev = slice(0, w["n_train"]), slice(w["n_train"], n_all)
+    log = lambda msg: print(f"learned: {msg}", file=sys.stderr, flush=True)  # noqa: E731
+
+    # training data from the decimation
+    t0 = time.perf_counter()
+    sig = torch.empty(n_all, 2, s, s, dtype=torch.complex128, device=dev)
+    it_dec = torch.empty(n_all, dtype=torch.int32, device=dev)
+    for c0 in range(0, w["n_train"], 1024):
+        c1 = min(c0 + 1024, w["n_train"])
+        ss.ss_lead_selfenergy(ctx, *lead, Ed[c0:c1].contiguous(), w["eta"], kidx=kid[c0:c1].contiguous(),
+                              sigma=sig[c0:c1], iters=it_dec[c0:c1])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    log(f"training data {t_data:.1f} s")
+    X = ss.ss_warm_features(ctx, Ed, kd)
+    mean, std = ss.ss_sigma_moments(ctx, sig[tr].contiguous(), std_floor=1e-6)
+    Y = ss.ss_sigma_encode(ctx, sig[tr].contiguous(), mean, std)
+    dims = [X.shape[1], w["width"], w["width"], w["width"], 4 * s * s]
+    net = ss.MLP(ctx, dims, seed=w["seed"])
+    g = torch.Generator(device="cpu").manual_seed(w["seed"])
+    t0 = time.perf_counter()
+    losses = []
+    for step in range(w["steps"]):
+        idx = torch.randint(0, w["n_train"], (w["batch"],), generator=g).to(dev)
+        xb, yb = X[idx].contiguous(), Y[idx].contiguous()
+        acts, _ = net.forward(xb)
+        loss = net.backward(xb, acts, yb)
+        net.adam(w["lr"])
+        if step % 100 == 0 or step == w["steps"] - 1:
+            losses.append(float(loss.item()))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"training {t_train:.1f} s, loss {losses[0]:.3f} -> {losses[-1]:.3f}")
+    del Y
+
+    Ee, ke, kie = Ed[ev].contiguous(), kd[ev].contiguous(), kid[ev].contiguous()
+    ne = w["n_eval"]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t
+
+    # cold: the decimation
+    (cold, _, _, info_c), t_cold = timed(lambda: ss.ss_lead_selfenergy(ctx, *lead, Ee, w["eta"], kidx=kie,
+                                                                       iters=it_dec[ev]))
+    ref = cold.clone()
+    it_cold = it_dec[ev].cpu().numpy()
+
+    # warm: features -> network -> Sigma -> Newton (judge, fallback)
+    def warm():
+        Xe = ss.ss_warm_features(ctx, Ee, ke)
+        _, pred = net.forward(Xe)
+        init = ss.ss_sigma_decode(ctx, pred.contiguous(), mean, std, s)
+        return init, ss.ss_lead_selfenergy_warm(ctx, *lead, Ee, w["eta"], init, kidx=kie)
+    (init_w, (sig_w, itn_w, itd_w, _, info_w)), t_warm = timed(warm)
+
+    # continuation: Newton from the self-energy of the nearest training point at the same momentum
+    E_np, ki_np = E, ki
+    near = np.empty(ne, dtype=np.int64)
+    for j in range(ne):
+        cand = np.nonzero(ki_np[tr] == ki_np[w["n_train"] + j])[0]
+        near[j] = cand[np.argmin(np.abs(E_np[cand] - E_np[w["n_train"] + j]))]
+    init_c = sig[torch.as_tensor(near).to(dev)].contiguous()
+    (sig_c, itn_c, itd_c, _, info_c2), t_cont = timed(
+        lambda: ss.ss_lead_selfenergy_warm(ctx, *lead, Ee, w["eta"], init_c, kidx=kie))
+
+    def rel_err(a, b):
+        d = (a - b).reshape(a.shape[0], -1).norm(dim=1) / b.reshape(b.shape[0], -1).norm(dim=1)
+        return d.cpu().numpy()
+
+    err_pred = rel_err(init_w, ref)
+    err_cont_start = rel_err(init_c, ref)
+    info_w, info_c2 = info_w.cpu().numpy(), info_c2.cpu().numpy()
+    out = {
+        "metric": "(E,k) self-energy solves/sec",
+        "value": round(ne / t_warm, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": round(t_warm * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "c128 (network fp32)",
+        "data": "synthetic",
+        "config": {"workload": "learned", "s": s, "n_train": w["n_train"], "n_eval": ne, "k_grid": w["nk"],
+                   "eta": w["eta"], "dims": dims, "train_steps": w["steps"], "batch": w["batch"]},
+        "cold_decimation": {"solves_per_s": round(ne / t_cold, 3), "iters": [int(it_cold.min()), int(it_cold.max())],
+                            "nonzero_info": int((info_c.cpu().numpy() != 0).sum())},
+        "warm_start": {"solves_per_s": round(ne / t_warm, 3), "accepted": int((info_w == 0).sum()),
+                       "fallback": int((info_w == -2).sum()), "newton_iters_max": int(itn_w.max()),
+                       "prediction_rel_err_median": float(np.median(err_pred)),
+                       "max_rel_diff_vs_cold": float(rel_err(sig_w, ref).max())},
+        "continuation": {"solves_per_s": round(ne / t_cont, 3), "accepted": int((info_c2 == 0).sum()),
+                         "start_rel_err_median": float(np.median(err_cont_start)),
+                         "max_rel_diff_vs_cold": float(rel_err(sig_c, ref).max())},
+        "training": {"data_s": round(t_data, 2), "train_s": round(t_train, 2), "loss_first": losses[0],
+                     "loss_last": losses[-1]},
+        "roofline": None,
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 class Pipeline:
     """The whole hot path for every instance of a workload, inputs resident on the GPU.
 
@@ -363,10 +500,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS) + ["uneven256"])
+    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS) + ["uneven256", "learned"])
     ap.add_argument("--no-graph", action="store_true", help="uneven256: enqueue eagerly instead of a graph replay")
     ap.add_argument("--no-autotune", action="store_true", help="uneven256: default panel widths and chunks")
-    ap.add_argument("--plan-mem-gib", type=float, default=32.0, help="uneven256: chunk work memory")
+    ap.add_argument("--plan-mem-gib", type=float, default=96.0, help="uneven256: chunk work memory")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
     ap.add_argument("--roofline-kernel", default="dec_update",
@@ -384,6 +521,8 @@ def main():
 
     if args.workload == "uneven256":
         return run_uneven(args)
+    if args.workload == "learned":
+        return run_learned(args)
     pipe = Pipeline(args.workload, args.chunk, args.mode)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel

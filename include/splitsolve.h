@@ -271,7 +271,8 @@ typedef struct {
 typedef struct {
   double eta;        /* broadening of the lead's diagonal cell (>= 0) */
   double sigma_tol;  /* decimation tolerance (0: 1e-14) */
-  int sigma_passes;  /* decimation passes enqueued (0: 64); converged instances skip later passes */
+  int sigma_passes;  /* decimation passes enqueued (0: ceil(log2(1/eta)) + 12, within [16, 200]);
+                        converged instances skip later passes, unconverged ones report info -1 */
   int m;             /* columns of psi (0: psi is not formed; then every instance's psi must be NULL) */
   int use_graph;     /* nonzero: capture the batch into one graph at creation */
   int autotune;      /* nonzero: time candidate panel widths and chunk sizes per group at creation */

@@ -241,10 +241,24 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
 
 using LuTile = TileCfg<64, 64, 16, 2, 2>;
 
+// the row map into LDS (n <= kLuMaxN, 256 threads): all loads are issued before the first store
 __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
-  for (int i = threadIdx.x; i < n; i += blockDim.x) sperm[i] = perm[i];
+  constexpr int NP = kLuMaxN / 256;
+  int v[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int i = threadIdx.x + e * 256;
+    v[e] = i < n ? perm[i] : 0;
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const int i = threadIdx.x + e * 256;
+    if (i < n) sperm[i] = v[e];
+  }
   __syncthreads();
 }
+
+static_assert(LuTile::NT == 256, "load_perm assumes 256 threads");
 
 // M[r][c] -= sum_{k in [k_lo, k_hi)} M[r][k] M[k][c] for logical rows [r_lo, r_hi), columns [c_lo, c_hi)
 __global__ void __launch_bounds__(LuTile::NT) k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
@@ -276,12 +290,14 @@ __global__ void __launch_bounds__(LuTile::NT) k_lu_gemm(LuArgs a, int r_lo, int 
 // In-tile triangular solve T x = c for the 64 columns of a staged tile, by substitution (LAPACK's
 // triangular-solve arithmetic).  Each wave owns 16 columns; 4 lanes share a column and each keeps the
 // rows j = part (mod 4), so a row step is a 4-lane partial dot product and two cross-lane additions.
-//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1);
-//   kUpper: false = unit lower (forward), true = upper with diagonal (backward); w <= W live rows.
-// out(i, col, x) receives every solved element of the rows i < w.
+//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1) holding only the
+//   strictly lower (!kUpper) or strictly upper (kUpper) entries, zero elsewhere;  rdiag: reciprocals of
+//   the diagonal (kUpper);  kUpper: false = unit lower (forward), true = upper (backward); w <= W rows.
+// Unsolved rows hold zero in x and the triangle is zero outside its part, so every row step reads the
+// whole row of the triangle unconditionally.  out(i, col, x) receives every solved element (i < w).
 template <int W, int kCP, bool kUpper, class Out>
-__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1], int w,
-                                          Out &&out) {
+__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1],
+                                          const double2 *rdiag, int w, Out &&out) {
   constexpr int NX = (W + 3) / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = wave * 16 + (lane >> 2), part = lane & 3;
@@ -295,8 +311,7 @@ __device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, co
 #pragma unroll
     for (int t = 0; t < NX; ++t) {
       const int j = part + 4 * t;
-      const bool use = kUpper ? (j > i && j < w) : (j < i);
-      const double lx = use ? tri[i][j].x : 0.0, ly = use ? tri[i][j].y : 0.0;
+      const double lx = tri[i][j].x, ly = tri[i][j].y;
       ax += lx * x[t].x - ly * x[t].y;
       ay += lx * x[t].y + ly * x[t].x;
     }
@@ -306,7 +321,7 @@ __device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, co
     ay += __shfl_xor(ay, 2);
     if (part == (i & 3)) {
       double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
-      if (kUpper) v = cmul(v, crecip(ld2(tri[i][i])));  // scaled reciprocal: no overflow of |u|^2
+      if (kUpper) v = cmul(v, ld2(rdiag[i]));
       const int ti = i >> 2;
 #pragma unroll
       for (int t = 0; t < NX; ++t) {
@@ -325,32 +340,60 @@ __device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, co
 // Leaf of the triangular solves: rows [r0, r0+w) of columns [c_lo, c_hi), in place, with the W x W
 // diagonal block at logical rows/columns r0 (unit lower if !kUpper, upper otherwise).
 template <int W, bool kUpper>
-__global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int c_lo, int c_hi) {
+__global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int rows, int c_lo, int c_hi) {
   constexpr int CP = 64 + 1;
   __shared__ double cr[W * CP], ci[W * CP];
   __shared__ double2 tri[W][W + 1];
+  __shared__ double2 rdiag[W];
   __shared__ int sp[W];
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
   const ColView cv = col_view(a, mat, c_lo);
   const int *perm = a.perm + (long)mat * a.sP;
-  const int w = min(W, a.n - r0);
+  const int w = min(min(W, rows), a.n - r0);
   const int c0 = c_lo + blockIdx.x * 64;
   if (threadIdx.x < W) sp[threadIdx.x] = threadIdx.x < w ? perm[r0 + threadIdx.x] : 0;
   __syncthreads();
-  for (int idx = threadIdx.x; idx < W * 64; idx += 256) {
-    const int i = idx / 64, c = idx % 64;
-    const double2 v = (i < w && c0 + c < c_hi) ? cv.p[(long)sp[i] * cv.ld + c0 + c] : make_double2(0.0, 0.0);
-    cr[i * CP + c] = v.x;
-    ci[i * CP + c] = v.y;
-  }
-  for (int idx = threadIdx.x; idx < W * W; idx += 256) {
-    const int i = idx / W, j = idx % W;
-    st2(tri[i][j], (i < w && j < w) ? M[(long)sp[i] * a.ldm + r0 + j] : make_double2(0.0, 0.0));
+  {
+    // every global load is issued before the first LDS store: the loads overlap instead of each paying
+    // the full memory latency in turn
+    constexpr int NV = (W * 64 + 255) / 256, NTR = (W * W + 255) / 256;
+    double2 v[NV], tv[NTR];
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int idx = threadIdx.x + e * 256, i = idx / 64, c = idx % 64;
+      v[e] = (idx < W * 64 && i < w && c0 + c < c_hi) ? cv.p[(long)sp[i] * cv.ld + c0 + c] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int e = 0; e < NTR; ++e) {
+      const int idx = threadIdx.x + e * 256, i = idx / W, j = idx % W;
+      tv[e] = (idx < W * W && i < w && j < w && (kUpper ? j >= i : j < i)) ? M[(long)sp[i] * a.ldm + r0 + j]
+                                                                          : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int e = 0; e < NV; ++e) {
+      const int idx = threadIdx.x + e * 256, i = idx / 64, c = idx % 64;
+      if (idx < W * 64) {
+        cr[i * CP + c] = v[e].x;
+        ci[i * CP + c] = v[e].y;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < NTR; ++e) {
+      const int idx = threadIdx.x + e * 256, i = idx / W, j = idx % W;
+      if (idx < W * W) {
+        if (kUpper && i == j) {  // the diagonal leaves the triangle for its scaled reciprocal
+          st2(rdiag[i], i < w ? crecip(tv[e]) : make_double2(0.0, 0.0));
+          st2(tri[i][j], make_double2(0.0, 0.0));
+        } else {
+          st2(tri[i][j], tv[e]);
+        }
+      }
+    }
   }
   __syncthreads();
-  tile_trsm<W, CP, kUpper>(cr, ci, tri, w, [&](int i, int col, double2 v) {
+  tile_trsm<W, CP, kUpper>(cr, ci, tri, rdiag, w, [&](int i, int col, double2 v) {
     if (c0 + col < c_hi) cv.p[(long)sp[i] * cv.ld + c0 + col] = v;
   });
 }
@@ -387,16 +430,18 @@ struct LuRun {
     hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi, c_lo, c_hi,
                        k_lo, k_hi);
   }
+  // triangular-solve leaves cover up to TL rows
+  static constexpr int TL = W;
   template <bool kUpper>
-  void leaf(int r0, int c_lo, int c_hi) {
+  void leaf(int r0, int rows, int c_lo, int c_hi) {
     if (c_lo >= c_hi) return;
     KernelScope ks_(ctx, "trsm");
-    hipLaunchKernelGGL((k_trsm_leaf<W, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream, a,
-                       r0, c_lo, c_hi);
+    hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream, a,
+                       r0, rows, c_lo, c_hi);
   }
   // unit lower solve on rows [lo, hi) of columns [c_lo, c_hi)
   void trsm_lower(int lo, int hi, int c_lo, int c_hi) {
-    if (hi - lo <= W) return leaf<false>(lo, c_lo, c_hi);
+    if (hi - lo <= TL) return leaf<false>(lo, hi - lo, c_lo, c_hi);
     const int m = mid(lo, hi);
     trsm_lower(lo, m, c_lo, c_hi);
     gemm(m, hi, c_lo, c_hi, lo, m);
@@ -404,7 +449,7 @@ struct LuRun {
   }
   // upper solve on rows [lo, hi) of columns [c_lo, c_hi)
   void trsm_upper(int lo, int hi, int c_lo, int c_hi) {
-    if (hi - lo <= W) return leaf<true>(lo, c_lo, c_hi);
+    if (hi - lo <= TL) return leaf<true>(lo, hi - lo, c_lo, c_hi);
     const int m = mid(lo, hi);
     trsm_upper(m, hi, c_lo, c_hi);
     gemm(lo, m, c_lo, c_hi, m, hi);

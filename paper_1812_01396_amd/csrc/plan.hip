@@ -9,6 +9,7 @@
 // into a single graph and replayed by one launch.  An autotuner times candidate LU panel widths and
 // chunk sizes per group on the group's own smallest instances before capture.
 #include <algorithm>
+#include <cmath>
 #include <map>
 #include <numeric>
 
@@ -324,7 +325,12 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
   p->n = n;
   p->inst.assign(inst, inst + n);
   p->opts = *opts;
-  if (p->opts.sigma_passes == 0) p->opts.sigma_passes = 64;
+  if (p->opts.sigma_passes == 0) {
+    // a decimation pass doubles the cell range and the broadening damps a propagating mode over about
+    // 1/eta cells, so about log2(1/eta) passes converge; a margin covers slow modes
+    const double eta = p->opts.eta > 0 ? p->opts.eta : 1e-60;
+    p->opts.sigma_passes = std::min(200, std::max(16, (int)std::ceil(std::log2(1.0 / eta)) + 12));
+  }
   if (p->opts.mem_bytes == 0) p->opts.mem_bytes = (size_t)32 << 30;
   p->T = T;
   p->info = info;
