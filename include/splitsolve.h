@@ -251,8 +251,9 @@ ss_status ss_lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const s
  * energy points independently side by side, Sec. 4).  A plan groups the instances by s, sorts each
  * group by nb and splits it into chunks that fit `mem_bytes`; a chunk runs the whole hot path
  * (self-energies, Step 1, Steps 2-4, Caroli T) in lockstep, launching at recursion step t only the
- * instances with more than t blocks.  Groups run on streams of their own.  With use_graph the whole
- * batch is captured once into one graph at creation and every ss_plan_execute is one graph launch.
+ * instances with more than t blocks.  Groups run on streams of their own.  With use_graph each group's
+ * work is captured once into a graph at creation and every ss_plan_execute is one graph launch per
+ * group (on the group's stream, all forked from and joined into one origin stream).
  * With autotune, candidate LU panel widths and chunk sizes are timed per group at creation.
  *
  * Instance blocks are device pointers owned by the caller and must stay valid and unmoved for the
@@ -274,7 +275,7 @@ typedef struct {
   int sigma_passes;  /* decimation passes enqueued (0: ceil(log2(1/eta)) + 12, within [16, 200]);
                         converged instances skip later passes, unconverged ones report info -1 */
   int m;             /* columns of psi (0: psi is not formed; then every instance's psi must be NULL) */
-  int use_graph;     /* nonzero: capture the batch into one graph at creation */
+  int use_graph;     /* nonzero: capture each size group's work into a graph at creation */
   int autotune;      /* nonzero: time candidate panel widths and chunk sizes per group at creation */
   size_t mem_bytes;  /* device memory for chunk work (0: 32 GiB); a chunk always holds one instance */
 } ss_plan_opts;
@@ -295,8 +296,8 @@ ss_status ss_plan_execute(ss_plan *plan);
 int ss_plan_groups(const ss_plan *plan);
 ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, int *chunk, int *lu_width,
                            double *tune_ms);
-/* Nodes of the captured graph (0 without use_graph); a negative value -n means a graph of n nodes was
- * captured but judged too large to instantiate (over 200000 nodes), and the plan runs as one
+/* Nodes of the captured group graphs, summed (0 without use_graph); a negative value -n means that a
+ * group graph came out larger than 8192 nodes (n summed over the groups), and the plan runs as one
  * sync-free enqueue of the same launches instead. */
 long long ss_plan_graph_nodes(const ss_plan *plan);
 /* Waits for the plan's work and frees it (it does not use the context: a plan may outlive it). */

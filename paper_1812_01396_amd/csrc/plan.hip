@@ -5,8 +5,8 @@
 // one tile shape), sort each group by block count nb (largest first) and split it into chunks that
 // fit the plan's memory.  A chunk runs the whole hot path in lockstep: at recursion step t only the
 // instances with more than t blocks are launched, so an uneven chunk does exactly its own work.
-// Groups run on their own streams and overlap.  The enqueued work of all groups can be captured once
-// into a single graph and replayed by one launch.  An autotuner times candidate LU panel widths and
+// Groups run on their own streams and overlap.  The enqueued work of each group can be captured once
+// into a graph of its own, so an execution is one graph launch per group.  An autotuner times candidate LU panel widths and
 // chunk sizes per group on the group's own smallest instances before capture.
 #include <algorithm>
 #include <cmath>
@@ -44,6 +44,9 @@ struct Group {
   ss_c128 *Q = nullptr, *sigma = nullptr, *inj = nullptr, *gc = nullptr;
   double *T = nullptr;
   int *info = nullptr;  // [4][chunk]
+  hipGraph_t graph = nullptr;  // the group's captured work (when the plan uses graphs)
+  hipGraphExec_t exec = nullptr;
+  size_t nodes = 0;
 };
 
 __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig, int count, int cap, double *T,
@@ -58,8 +61,11 @@ __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig,
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// largest captured graph that is instantiated; larger plans run as a sync-free enqueue
-constexpr size_t kMaxGraphNodes = 200000;
+// Largest captured group graph that is instantiated; a plan with a larger one runs as a sync-free
+// enqueue of the same launches.  Instantiating captured graphs of about 10^5 kernel nodes (long single
+// dependency chains) ended the host process with a segmentation fault in this runtime, while graphs of
+// a few thousand nodes replay correctly; the bound keeps instantiation to the range that was exercised.
+constexpr size_t kMaxGraphNodes = 8192;
 
 }  // namespace
 
@@ -74,10 +80,9 @@ struct ss_plan {
   std::vector<Group> groups;
   hipEvent_t start = nullptr, finish = nullptr;
   hipStream_t origin = nullptr;  // the stream the batch forks from (captured when a graph is built)
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
-  size_t graph_nodes = 0;
-  long long graph_refused = 0;  // nodes of a captured graph judged too large to instantiate
+  bool graphs = false;           // every group replays its own captured graph
+  size_t graph_nodes = 0;       // summed over the groups
+  long long graph_refused = 0;  // nodes of a captured group graph judged too large to instantiate
 };
 
 namespace {
@@ -219,16 +224,56 @@ ss_status run_group(ss_plan *p, Group &g) {
   return SS_OK;
 }
 
-// Enqueue the whole batch on `origin`: every group forks from it and joins back into it.
+// Enqueue the whole batch on `origin`: every group forks from it and joins back into it.  With graphs,
+// each group's work is one launch of its captured graph on its stream.
 ss_status enqueue(ss_plan *p, hipStream_t origin) {
   if (hipEventRecord(p->start, origin) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: event record failed");
   for (Group &g : p->groups) {
     if (hipStreamWaitEvent(g.stream, p->start, 0) != hipSuccess)
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: stream wait failed");
-    SS_TRY(run_group(p, g));
+    if (p->graphs) {
+      if (hipGraphLaunch(g.exec, g.stream) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: graph launch failed");
+    } else {
+      SS_TRY(run_group(p, g));
+    }
     if (hipEventRecord(g.done, g.stream) != hipSuccess || hipStreamWaitEvent(origin, g.done, 0) != hipSuccess)
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: join failed");
   }
+  return SS_OK;
+}
+
+// Capture every group's work into a graph of its own (capture on the group's stream).  A group whose
+// graph exceeds kMaxGraphNodes makes the plan fall back to the sync-free enqueue for all groups.
+ss_status capture_groups(ss_plan *p) {
+  size_t total = 0;
+  bool too_big = false;
+  for (Group &g : p->groups) {
+    if (hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: stream capture could not start");
+    const ss_status st = run_group(p, g);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g.stream, &graph);
+    g.graph = graph;
+    if (st != SS_OK) return st;
+    if (ec != hipSuccess || !graph) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: capture failed");
+    if (hipGraphGetNodes(g.graph, nullptr, &g.nodes) != hipSuccess)
+      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph node count failed");
+    total += g.nodes;
+    if (g.nodes > kMaxGraphNodes) too_big = true;
+  }
+  if (too_big) {
+    p->graph_refused = (long long)total;
+    for (Group &g : p->groups) {
+      (void)hipGraphDestroy(g.graph);
+      g.graph = nullptr;
+    }
+    return SS_OK;
+  }
+  for (Group &g : p->groups)
+    if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess)
+      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed");
+  p->graphs = true;
+  p->graph_nodes = total;
   return SS_OK;
 }
 
@@ -280,10 +325,10 @@ ss_status autotune(ss_plan *p, Group &g, int chunk_max) {
 
 void release(ss_plan *p) {
   if (p->origin) (void)hipStreamSynchronize(p->origin);
-  if (p->exec) (void)hipGraphExecDestroy(p->exec);
-  if (p->graph) (void)hipGraphDestroy(p->graph);
   for (Group &g : p->groups) {
     if (g.stream) (void)hipStreamSynchronize(g.stream);
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
     if (g.ctx) ss_destroy(g.ctx);
     if (g.tables) (void)hipFree(g.tables);
     if (g.work) (void)hipFree(g.work);
@@ -399,28 +444,8 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
     return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: first pass failed"));
   for (Group &g : p->groups) g.ctx->sync_free = true;
   if (p->opts.use_graph) {
-    if (hipStreamBeginCapture(p->origin, hipStreamCaptureModeThreadLocal) != hipSuccess)
-      return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: stream capture could not start"));
-    st = enqueue(p, p->origin);
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(p->origin, &graph);
-    p->graph = graph;
+    st = capture_groups(p);
     if (st != SS_OK) return bail(st);
-    if (ec != hipSuccess || !graph) return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: capture failed"));
-    size_t nodes = 0;
-    if (hipGraphGetNodes(p->graph, nullptr, &nodes) != hipSuccess)
-      return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: graph node count failed"));
-    if (nodes > kMaxGraphNodes) {
-      // too large to instantiate as one graph: the plan runs as one sync-free enqueue instead
-      (void)hipGraphDestroy(p->graph);
-      p->graph = nullptr;
-      p->graph_nodes = 0;
-      p->graph_refused = (long long)nodes;
-    } else {
-      if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
-        return bail(fail(ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed"));
-      p->graph_nodes = nodes;
-    }
   }
   *out = p;
   return SS_OK;
@@ -434,12 +459,7 @@ ss_status ss_plan_execute(ss_plan *p) {
   // ordered after the work already on the caller's stream, and the caller's stream after the batch
   if (hipEventRecord(p->finish, ctx->stream) != hipSuccess || hipStreamWaitEvent(p->origin, p->finish, 0) != hipSuccess)
     return fail(ctx, SS_ERR_DEVICE, "ss_plan_execute: stream ordering failed");
-  if (p->exec) {
-    if (hipGraphLaunch(p->exec, p->origin) != hipSuccess)
-      return fail(ctx, SS_ERR_DEVICE, "ss_plan_execute: graph launch failed");
-  } else {
-    SS_TRY(enqueue(p, p->origin));
-  }
+  SS_TRY(enqueue(p, p->origin));
   if (hipEventRecord(p->finish, p->origin) != hipSuccess || hipStreamWaitEvent(ctx->stream, p->finish, 0) != hipSuccess)
     return fail(ctx, SS_ERR_DEVICE, "ss_plan_execute: stream ordering failed");
   return SS_OK;

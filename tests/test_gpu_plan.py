@@ -126,6 +126,7 @@ def test_plan_graph_replays_match_eager(ctx, batch):
     psi0 = [x.psi.cpu().numpy() for x in xe]
     xg = _make(ss, insts, Es, m)
     graph = ss.Plan(ctx, xg, ETA, m=m, use_graph=True, autotune=False)
+    print("graph nodes", graph.graph_nodes, flush=True)
     assert graph.graph_nodes > 0
     for rep in range(3):
         graph.T.zero_()
