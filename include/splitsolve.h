@@ -81,14 +81,17 @@ size_t ss_workspace_bytes(const ss_ctx *ctx);
  * the accumulated time and from then on brackets every launch of that kernel family on this context
  * with a pair of HIP events on the context's stream (NULL or "" switches the probe off).
  * ss_kernel_timer_read waits for the stream and returns the summed event time in milliseconds, the
- * number of timed launches and (flops, may be NULL) the algorithmic flops of those launches where the
- * launch site states them (8 m n k per complex product; "lu_gemm" only, else 0) since the last read,
- * then clears them.  Families: "form" (diagonal block formation and product of the recursion),
+ * number of timed launches, (flops, may be NULL) the algorithmic flops of those launches where the
+ * launch site states them (8 m n k per complex product; "lu_gemm" only, else 0) and (bytes, may be
+ * NULL) their algorithmic HBM bytes (each operand read once and the result written once: 16 (m k +
+ * k n + 2 m n) per complex m x n x k update; "lu_gemm" only, else 0) since the last read, then clears
+ * them.  Families: "form" (diagonal block formation and product of the recursion),
  * "chain" (Q_i = -X_i Q_{i-1}), "panel" (LU panel factorization), "lu_gemm" (LU trailing and
  * triangular-solve products), "trsm" (triangular-solve leaves), "dec_update" (decimation pass
  * products), "obc" (corner system and psi products), "trans" (transmission). */
 ss_status ss_kernel_timer(ss_ctx *ctx, const char *family);
-ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops);
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops,
+                               double *bytes);
 
 /* ---------------------------------------------------------------- inputs */
 

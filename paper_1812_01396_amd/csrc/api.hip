@@ -63,12 +63,13 @@ static hipEvent_t timer_event(ss_ctx *ctx) {
   return ctx->timer_events[ctx->timer_used++];
 }
 
-KernelScope::KernelScope(ss_ctx *c, const char *family, double flops) : ctx(c), on(false) {
+KernelScope::KernelScope(ss_ctx *c, const char *family, double flops, double bytes) : ctx(c), on(false) {
   if (!ctx->timer_family.empty() && ctx->timer_family == family) {
     hipEvent_t e = timer_event(ctx);
     if (e && hipEventRecord(e, ctx->stream) == hipSuccess) {
       on = true;
       ctx->timer_flops += flops;
+      ctx->timer_bytes += bytes;
     }
   }
 }
@@ -162,10 +163,12 @@ ss_status ss_kernel_timer(ss_ctx *ctx, const char *family) {
   ctx->timer_family = family ? family : "";
   ctx->timer_used = 0;
   ctx->timer_flops = 0.0;
+  ctx->timer_bytes = 0.0;
   return SS_OK;
 }
 
-ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops) {
+ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops,
+                               double *bytes) {
   SS_TRY(enter(ctx));
   if (!total_ms || !launches) return fail(ctx, SS_ERR_ARG, "ss_kernel_timer_read: null output");
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");
@@ -180,8 +183,10 @@ ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launche
   *total_ms = t;
   *launches = (long long)pairs;
   if (flops) *flops = ctx->timer_flops;
+  if (bytes) *bytes = ctx->timer_bytes;
   ctx->timer_used = 0;
   ctx->timer_flops = 0.0;
+  ctx->timer_bytes = 0.0;
   return SS_OK;
 }
 

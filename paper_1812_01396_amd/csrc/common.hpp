@@ -90,6 +90,7 @@ struct ss_ctx {
   std::vector<hipEvent_t> timer_events;
   size_t timer_used = 0;
   double timer_flops = 0.0;  // algorithmic flops of the timed launches (where the launch site states them)
+  double timer_bytes = 0.0;  // algorithmic HBM bytes of the same launches (operands read once, results written once)
 };
 
 namespace ss {
@@ -104,7 +105,7 @@ ss_status host_word(ss_ctx *ctx, int **out);
 struct KernelScope {
   ss_ctx *ctx;
   bool on;
-  KernelScope(ss_ctx *c, const char *family, double flops = 0.0);
+  KernelScope(ss_ctx *c, const char *family, double flops = 0.0, double bytes = 0.0);
   ~KernelScope();
 };
 

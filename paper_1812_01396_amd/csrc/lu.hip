@@ -426,7 +426,8 @@ struct LuRun {
   void gemm(int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int k_hi) {
     if (r_lo >= r_hi || c_lo >= c_hi || k_lo >= k_hi) return;
     const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
-    KernelScope ks_(ctx, "lu_gemm", 8.0 * (r_hi - r_lo) * (double)(c_hi - c_lo) * (k_hi - k_lo) * d.nmat);
+    const double m_ = r_hi - r_lo, n_ = c_hi - c_lo, k_ = k_hi - k_lo;
+    KernelScope ks_(ctx, "lu_gemm", 8.0 * m_ * n_ * k_ * d.nmat, 16.0 * (m_ * k_ + k_ * n_ + 2.0 * m_ * n_) * d.nmat);
     hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi, c_lo, c_hi,
                        k_lo, k_hi);
   }

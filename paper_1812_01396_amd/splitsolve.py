@@ -95,7 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_workspace_bytes.restype = Z
     lib.ss_kernel_timer.argtypes = [P, ctypes.c_char_p]
     lib.ss_kernel_timer.restype = I
-    lib.ss_kernel_timer_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D)]
+    lib.ss_kernel_timer_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D),
+                                         ctypes.POINTER(D)]
     lib.ss_kernel_timer_read.restype = I
     lib.ss_lead_selfenergy.argtypes = [P, I, I, I, P, P, P, P, P, P, D, D, I, P, P, P, P]
     lib.ss_lead_selfenergy.restype = I
@@ -221,10 +222,12 @@ class Context:
         self.check(self.lib.ss_kernel_timer(self.handle, family.encode() if family else None))
 
     def kernel_timer_read(self, with_flops: bool = False):
-        """(summed milliseconds, launches[, stated flops]) of the timed family since the last read."""
-        ms, n, fl = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double()
-        self.check(self.lib.ss_kernel_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl)))
-        return (ms.value, n.value, fl.value) if with_flops else (ms.value, n.value)
+        """(summed milliseconds, launches[, stated flops, stated bytes]) of the timed family since the last
+        read."""
+        ms, n, fl, by = ctypes.c_double(), ctypes.c_longlong(), ctypes.c_double(), ctypes.c_double()
+        self.check(self.lib.ss_kernel_timer_read(self.handle, ctypes.byref(ms), ctypes.byref(n), ctypes.byref(fl),
+                                                 ctypes.byref(by)))
+        return (ms.value, n.value, fl.value, by.value) if with_flops else (ms.value, n.value)
 
 
 def ss_lead_selfenergy(ctx: Context, H00, H01, S00, S01, E, eta: float, tol: float = 0.0, max_iter: int = 0,
