@@ -240,6 +240,8 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
 // ------------------------------------------------------------------ products and triangular leaves
 
 using LuTile = TileCfg<64, 64, 16, 2, 2>;
+// products of at most 32 rows (the deepest levels of the triangular solves): one row of four waves
+using LuTileFlat = TileCfg<32, 128, 16, 1, 4>;
 
 // the row map into LDS (n <= kLuMaxN, 256 threads): all loads are issued before the first store
 __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
@@ -261,9 +263,10 @@ __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
 static_assert(LuTile::NT == 256, "load_perm assumes 256 threads");
 
 // M[r][c] -= sum_{k in [k_lo, k_hi)} M[r][k] M[k][c] for logical rows [r_lo, r_hi), columns [c_lo, c_hi)
-__global__ void __launch_bounds__(LuTile::NT) k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi, int k_lo,
-                                                         int k_hi) {
-  using T = LuTile;
+template <class T>
+__global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi,
+                                                                int k_lo, int k_hi) {
+  static_assert(T::NT == 256, "load_perm assumes 256 threads");
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sperm[kLuMaxN];
   const int mat = blockIdx.y;
@@ -425,11 +428,17 @@ struct LuRun {
 
   void gemm(int r_lo, int r_hi, int c_lo, int c_hi, int k_lo, int k_hi) {
     if (r_lo >= r_hi || c_lo >= c_hi || k_lo >= k_hi) return;
-    const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
     const double m_ = r_hi - r_lo, n_ = c_hi - c_lo, k_ = k_hi - k_lo;
     KernelScope ks_(ctx, "lu_gemm", 8.0 * m_ * n_ * k_ * d.nmat, 16.0 * (m_ * k_ + k_ * n_ + 2.0 * m_ * n_) * d.nmat);
-    hipLaunchKernelGGL(k_lu_gemm, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi, c_lo, c_hi,
-                       k_lo, k_hi);
+    if (r_hi - r_lo <= LuTileFlat::BM && c_hi - c_lo > LuTileFlat::BN / 2) {
+      const int tiles = cdiv(c_hi - c_lo, LuTileFlat::BN);
+      hipLaunchKernelGGL(k_lu_gemm<LuTileFlat>, dim3(tiles, d.nmat), dim3(LuTileFlat::NT), 0, ctx->stream, a, r_lo,
+                         r_hi, c_lo, c_hi, k_lo, k_hi);
+    } else {
+      const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
+      hipLaunchKernelGGL(k_lu_gemm<LuTile>, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi,
+                         c_lo, c_hi, k_lo, k_hi);
+    }
   }
   // triangular-solve leaves cover up to TL rows
   static constexpr int TL = W;

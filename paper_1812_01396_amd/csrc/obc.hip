@@ -69,7 +69,7 @@ __device__ __forceinline__ const double2 *obc_q(const ObcArgs &a, int inst) {
   return a.Q + (a.boff ? a.boff[inst] : (long)inst * a.nb) * 2 * (long)a.s * a.s;
 }
 
-__global__ void __launch_bounds__(ObcTile::NT) k_obc_cq(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cq(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, nb = obc_nb(a, inst);
@@ -102,7 +102,7 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_cq(ObcArgs a) {
 }
 
 // C Q b' into the last m columns of the augmented matrix
-__global__ void __launch_bounds__(ObcTile::NT) k_obc_cqb(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cqb(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;
@@ -122,7 +122,7 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_cqb(ObcArgs a) {
 }
 
 // gc = Q_c V
-__global__ void __launch_bounds__(ObcTile::NT) k_obc_gc(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_gc(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s;
@@ -142,7 +142,7 @@ __global__ void __launch_bounds__(ObcTile::NT) k_obc_gc(ObcArgs a) {
 }
 
 // psi = Q (b' + z): rows nb*s, columns m, depth 2s
-__global__ void __launch_bounds__(ObcTile::NT) k_obc_psi(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_psi(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;

@@ -62,7 +62,7 @@ __device__ __forceinline__ int ref_set(const RefArgs &a, int inst) {
 }
 
 // r = B b' - T x for every block, with ||r||^2 and ||B b'||^2; grid (nb * tiles(s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) k_ref_resid(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_resid(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ double red[2][T::NT / 64];
@@ -147,7 +147,7 @@ __global__ void k_ref_check(RefArgs a, int it, int *iters, double *resid) {
 }
 
 // r_i -= A_{i,i+1} g_{i+1}
-__global__ void __launch_bounds__(RefTile::NT) k_ref_couple(RefArgs a, int i) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_couple(RefArgs a, int i) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -171,7 +171,7 @@ __global__ void __launch_bounds__(RefTile::NT) k_ref_couple(RefArgs a, int i) {
 }
 
 // y_i = g_i - X_i y_{i-1} (in place in g); X_i of block i was kept at slot nb-1-i of the even system
-__global__ void __launch_bounds__(RefTile::NT) k_ref_chain(RefArgs a, int i) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_chain(RefArgs a, int i) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(RefTile::NT) k_ref_chain(RefArgs a, int i) {
 }
 
 // C y = [Sigma_L y_1; Sigma_R y_nb]; grid (2 * tiles(s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) k_ref_cy(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_cy(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -216,7 +216,7 @@ __global__ void __launch_bounds__(RefTile::NT) k_ref_cy(RefArgs a) {
 }
 
 // x += y + Q z; grid (tiles(nb s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) k_ref_update(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_update(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -439,7 +439,7 @@ __global__ void __launch_bounds__(1024) k_inject_left(const double2 *sigma, int 
 using TpTile = TileCfg<64, 64, 16, 2, 2>;
 
 // partial sums of Re sum_{a,c} conj(psi[a][c]) (Gamma_R psi)[a][c] over tiles of the last block row
-__global__ void __launch_bounds__(TpTile::NT) k_trans_psi(const double2 *psi, const double2 *sigma, int nb, int s,
+__global__ void __launch_bounds__(TpTile::NT) SS_TILE_WAVES k_trans_psi(const double2 *psi, const double2 *sigma, int nb, int s,
                                                            int m, double *partial) {
   using T = TpTile;
   __shared__ double lds[T::LDS_DOUBLES];

@@ -108,7 +108,7 @@ __global__ void k_dec_reset(DecArgs a) {
 using DecTile = TileCfg<64, 64, 16, 2, 2>;
 
 // One decimation pass for tile (m0, n0) of every s x s block, from Y = [G beta | G alpha].
-__global__ void __launch_bounds__(DecTile::NT) k_dec_update(DecArgs a, int par) {
+__global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_update(DecArgs a, int par) {
   using T = DecTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s;
@@ -240,7 +240,7 @@ __global__ void k_dec_final_form(DecArgs a, double2 *M2, const double2 *sigma, i
 
 // Sigma_R = a1 W_R (system 2i), Sigma_L = am1 W_L (system 2i+1).  residual != 0: instead accumulate
 // ||Sigma - a W||_F^2 and ||Sigma||_F^2 into acc2[sys][2].
-__global__ void __launch_bounds__(DecTile::NT) k_dec_sigma(DecArgs a, const double2 *Wsol, double2 *sigma,
+__global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_sigma(DecArgs a, const double2 *Wsol, double2 *sigma,
                                                            double *acc2, int residual) {
   using T = DecTile;
   __shared__ double lds[T::LDS_DOUBLES];

@@ -86,7 +86,8 @@ __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0,
 
 // Forms [D | RHS] of step t for every system; fold the previous step's zero pivot into `code`.
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) k_form(SweepArgs a, int t) {
+__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(kF32 ? 1 : 3)))
+k_form(SweepArgs a, int t) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
@@ -188,7 +189,8 @@ __global__ void k_code_init(int *code, int n) {
 
 // Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) k_chain(SweepArgs a, int u) {
+__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(kF32 ? 1 : 3)))
+k_chain(SweepArgs a, int u) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;

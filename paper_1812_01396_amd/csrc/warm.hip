@@ -165,7 +165,7 @@ __global__ void k_warm_check(WarmArgs a, int it, int max_newton) {
 }
 
 // T = D N_j
-__global__ void __launch_bounds__(WTile::NT) k_smith_t(WarmArgs a, int par) {
+__global__ void __launch_bounds__(WTile::NT) SS_TILE_WAVES k_smith_t(WarmArgs a, int par) {
   using T = WTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int sys = blockIdx.y;
@@ -183,7 +183,7 @@ __global__ void __launch_bounds__(WTile::NT) k_smith_t(WarmArgs a, int par) {
 }
 
 // D += M_j T with |term|^2 and |D|^2
-__global__ void __launch_bounds__(WTile::NT) k_smith_term(WarmArgs a, int par) {
+__global__ void __launch_bounds__(WTile::NT) SS_TILE_WAVES k_smith_term(WarmArgs a, int par) {
   using T = WTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int sys = blockIdx.y;
@@ -233,7 +233,7 @@ __global__ void k_smith_check(WarmArgs a, int last) {
 }
 
 // M_{j+1} = c^2 M_j^2, N_{j+1} = N_j^2 / c^2 with their norms
-__global__ void __launch_bounds__(WTile::NT) k_smith_square(WarmArgs a, int par) {
+__global__ void __launch_bounds__(WTile::NT) SS_TILE_WAVES k_smith_square(WarmArgs a, int par) {
   using T = WTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int sys = blockIdx.y;
@@ -306,7 +306,7 @@ __global__ void k_pow_norm_init(WarmArgs a) {
 }
 
 // Q = P^2 (unnormalised), |Q|^2
-__global__ void __launch_bounds__(WTile::NT) k_pow_square(WarmArgs a, int par) {
+__global__ void __launch_bounds__(WTile::NT) SS_TILE_WAVES k_pow_square(WarmArgs a, int par) {
   using T = WTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int sys = blockIdx.y;
