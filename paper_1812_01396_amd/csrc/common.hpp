@@ -67,6 +67,7 @@ enum Slot {
   kSlotWarmMisc,
   kSlotMlp,        // split-K partial products of the network
   kSlotMlpDz,      // back-propagated gradients
+  kSlotLuInv,      // inverses of the LU's diagonal blocks (triangular-solve leaves)
   kNumSlots
 };
 

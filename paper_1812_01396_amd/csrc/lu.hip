@@ -48,6 +48,10 @@ struct LuArgs {
   double2 *B;  // right-hand sides (columns >= n) when non-null
   long sB;
   int ldb;
+  // inverses of the W x W diagonal blocks of L and U, written by the panels ([mat][panel][L, U][W][W]);
+  // null: the triangular-solve leaves substitute instead
+  double2 *inv;
+  long sInv;
 };
 
 // Base pointer and leading dimension for columns starting at c of system mat: columns >= n live in the
@@ -71,12 +75,65 @@ static LuArgs make_args(const LuDesc &d) {
   a.zp = d.zp; a.X = d.X; a.sX = d.sX; a.xoff = d.xoff; a.ldx = d.ldx; a.n = d.n; a.nrhs = d.nrhs;
   a.skip = d.skip; a.skip_shift = d.skip_shift;
   a.B = d.B; a.sB = d.sB; a.ldb = d.ldb;
+  a.inv = nullptr; a.sInv = 0;
   return a;
 }
 
 __global__ void k_identity_perm(int *perm, long sP, int n) {
   int *p = perm + (long)blockIdx.y * sP;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+// ------------------------------------------------------------------ in-tile triangular solve
+
+// In-tile triangular solve T x = c for the 64 columns of a staged tile, by substitution (LAPACK's
+// triangular-solve arithmetic).  Each wave owns 16 columns; 4 lanes share a column and each keeps the
+// rows j = part (mod 4), so a row step is a 4-lane partial dot product and two cross-lane additions.
+//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1) holding only the
+//   strictly lower (!kUpper) or strictly upper (kUpper) entries, zero elsewhere;  rdiag: reciprocals of
+//   the diagonal (kUpper);  kUpper: false = unit lower (forward), true = upper (backward); w <= W rows.
+// Unsolved rows hold zero in x and the triangle is zero outside its part, so every row step reads the
+// whole row of the triangle unconditionally.  out(i, col, x) receives every solved element (i < w).
+template <int W, int kCP, bool kUpper, class Out>
+__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1],
+                                          const double2 *rdiag, int w, Out &&out) {
+  constexpr int NX = (W + 3) / 4;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = wave * 16 + (lane >> 2), part = lane & 3;
+  double2 x[NX];
+#pragma unroll
+  for (int t = 0; t < NX; ++t) x[t] = make_double2(0.0, 0.0);
+#pragma unroll 1
+  for (int step = 0; step < w; ++step) {
+    const int i = kUpper ? w - 1 - step : step;
+    double ax = 0.0, ay = 0.0;
+#pragma unroll
+    for (int t = 0; t < NX; ++t) {
+      const int j = part + 4 * t;
+      const double lx = tri[i][j].x, ly = tri[i][j].y;
+      ax += lx * x[t].x - ly * x[t].y;
+      ay += lx * x[t].y + ly * x[t].x;
+    }
+    ax += __shfl_xor(ax, 1);
+    ay += __shfl_xor(ay, 1);
+    ax += __shfl_xor(ax, 2);
+    ay += __shfl_xor(ay, 2);
+    if (part == (i & 3)) {
+      double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
+      if (kUpper) v = cmul(v, ld2(rdiag[i]));
+      const int ti = i >> 2;
+#pragma unroll
+      for (int t = 0; t < NX; ++t) {
+        x[t].x = (t == ti) ? v.x : x[t].x;
+        x[t].y = (t == ti) ? v.y : x[t].y;
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NX; ++t) {
+    const int j = part + 4 * t;
+    if (j < w) out(j, col, x[t]);
+  }
 }
 
 // ------------------------------------------------------------------ panel factorization
@@ -98,6 +155,12 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   const long ld = a.ldm;
 
   __shared__ int sperm[LB * R];
+  // inversion of the diagonal block: its strict lower and strict upper triangles, the reciprocals of
+  // its diagonal and identity right-hand sides as real and imaginary planes
+  constexpr int CP = 64 + 1;
+  __shared__ double2 tri_l[W][W + 1], tri_u[W][W + 1];
+  __shared__ double2 rdiag[W];
+  __shared__ double eye_r[W * CP], eye_i[W * CP];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ double2 rowbuf[2][W];
@@ -220,6 +283,30 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   }
   __syncthreads();  // sperm final
 
+  if (a.inv != nullptr) {
+    // ---- inverses of the diagonal block's unit-lower and upper triangles (the triangular-solve leaves
+    // multiply by these on the matrix cores): the in-tile substitution applied to identity columns,
+    // by the first four waves (the panel is launched with at least 256 threads)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      const int lr = tid + q * T;
+      if (lr < W) {
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+          const bool in = lr < w && c < w;
+          st2(tri_l[lr][c], in && c < lr ? v[q * W + c] : make_double2(0.0, 0.0));
+          st2(tri_u[lr][c], in && c > lr ? v[q * W + c] : make_double2(0.0, 0.0));
+          if (c == lr) st2(rdiag[lr], in ? crecip(v[q * W + c]) : make_double2(0.0, 0.0));
+        }
+      }
+    }
+    for (int idx = tid; idx < W * CP; idx += T) {
+      const int i = idx / CP, c = idx % CP;
+      eye_r[idx] = (i == c && i < w) ? 1.0 : 0.0;
+      eye_i[idx] = 0.0;
+    }
+  }
+
   // ---- write the factored panel back (rows stay in their physical place) and the row map
 #pragma unroll
   for (int q = 0; q < R; ++q) {
@@ -234,6 +321,18 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   if (tid == 0) {
     if (c0 == 0) a.zp[mat] = zero_col;
     else if (zero_col != 0 && a.zp[mat] == 0) a.zp[mat] = zero_col;
+  }
+  if (a.inv != nullptr) {  // (after the write-back, so the panel's registers are free)
+    __syncthreads();
+    double2 *dst = a.inv + (long)mat * a.sInv + (long)(c0 / W) * 2 * W * W;
+    if (tid < 256) {
+      tile_trsm<W, CP, false>(eye_r, eye_i, tri_l, rdiag, w, [&](int i, int col, double2 x) {
+        if (col < w) dst[i * W + col] = x;
+      });
+      tile_trsm<W, CP, true>(eye_r, eye_i, tri_u, rdiag, w, [&](int i, int col, double2 x) {
+        if (col < w) dst[W * W + i * W + col] = x;
+      });
+    }
   }
 }
 
@@ -288,56 +387,6 @@ __global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm(LuArgs a, int r
       *p = csub(*p, val);
     }
   });
-}
-
-// In-tile triangular solve T x = c for the 64 columns of a staged tile, by substitution (LAPACK's
-// triangular-solve arithmetic).  Each wave owns 16 columns; 4 lanes share a column and each keeps the
-// rows j = part (mod 4), so a row step is a 4-lane partial dot product and two cross-lane additions.
-//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1) holding only the
-//   strictly lower (!kUpper) or strictly upper (kUpper) entries, zero elsewhere;  rdiag: reciprocals of
-//   the diagonal (kUpper);  kUpper: false = unit lower (forward), true = upper (backward); w <= W rows.
-// Unsolved rows hold zero in x and the triangle is zero outside its part, so every row step reads the
-// whole row of the triangle unconditionally.  out(i, col, x) receives every solved element (i < w).
-template <int W, int kCP, bool kUpper, class Out>
-__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1],
-                                          const double2 *rdiag, int w, Out &&out) {
-  constexpr int NX = (W + 3) / 4;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int col = wave * 16 + (lane >> 2), part = lane & 3;
-  double2 x[NX];
-#pragma unroll
-  for (int t = 0; t < NX; ++t) x[t] = make_double2(0.0, 0.0);
-#pragma unroll 1
-  for (int step = 0; step < w; ++step) {
-    const int i = kUpper ? w - 1 - step : step;
-    double ax = 0.0, ay = 0.0;
-#pragma unroll
-    for (int t = 0; t < NX; ++t) {
-      const int j = part + 4 * t;
-      const double lx = tri[i][j].x, ly = tri[i][j].y;
-      ax += lx * x[t].x - ly * x[t].y;
-      ay += lx * x[t].y + ly * x[t].x;
-    }
-    ax += __shfl_xor(ax, 1);
-    ay += __shfl_xor(ay, 1);
-    ax += __shfl_xor(ax, 2);
-    ay += __shfl_xor(ay, 2);
-    if (part == (i & 3)) {
-      double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
-      if (kUpper) v = cmul(v, ld2(rdiag[i]));
-      const int ti = i >> 2;
-#pragma unroll
-      for (int t = 0; t < NX; ++t) {
-        x[t].x = (t == ti) ? v.x : x[t].x;
-        x[t].y = (t == ti) ? v.y : x[t].y;
-      }
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < NX; ++t) {
-    const int j = part + 4 * t;
-    if (j < w) out(j, col, x[t]);
-  }
 }
 
 // Leaf of the triangular solves: rows [r0, r0+w) of columns [c_lo, c_hi), in place, with the W x W
@@ -401,6 +450,35 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int rows, i
   });
 }
 
+// Leaf of the triangular solves on the matrix cores: rows [r0, r0+w) of columns [c_lo, c_hi) are
+// replaced by T^{-1} times themselves, with T^{-1} the inverse of the W x W diagonal block at logical
+// row/column r0 (unit lower if !kUpper, upper otherwise) kept by its panel; r0 is a multiple of W.
+// Every workgroup reads all w rows of its columns before it writes them, so the update is in place.
+template <bool kUpper>
+__global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W, int r0, int rows,
+                                                                           int c_lo, int c_hi) {
+  using T = LuTileFlat;
+  __shared__ double lds[T::LDS_DOUBLES];
+  __shared__ int sp[T::BM];
+  const int mat = blockIdx.y;
+  if (skipped(a, mat)) return;
+  const ColView cv = col_view(a, mat, c_lo);
+  const int w = min(min(W, rows), a.n - r0);
+  if (threadIdx.x < T::BM) sp[threadIdx.x] = threadIdx.x < w ? a.perm[(long)mat * a.sP + r0 + threadIdx.x] : 0;
+  __syncthreads();
+  const int n0 = c_lo + blockIdx.x * T::BN;
+  const double2 *inv = a.inv + (long)mat * a.sInv + ((long)(r0 / W) * 2 + (kUpper ? 1 : 0)) * W * W;
+  Acc<T> acc;
+  acc.zero();
+  LdRow la{inv, W};
+  LdRowPerm lb{cv.p, cv.ld, sp};
+  mma_loop<T>(la, lb, 0, w, n0, c_hi, 0, w, acc, lds);
+  acc_foreach<T>(acc, [&](int r, int c, double2 val) {
+    const int gc = n0 + c;
+    if (r < w && gc < c_hi) cv.p[(long)sp[r] * cv.ld + gc] = val;
+  });
+}
+
 // X[r][c] = M[perm[r]][n + c]: the solution rows in natural order
 __global__ void k_copy_out(LuArgs a) {
   const int mat = blockIdx.y;
@@ -446,8 +524,12 @@ struct LuRun {
   void leaf(int r0, int rows, int c_lo, int c_hi) {
     if (c_lo >= c_hi) return;
     KernelScope ks_(ctx, "trsm");
-    hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream, a,
-                       r0, rows, c_lo, c_hi);
+    if (a.inv != nullptr)
+      hipLaunchKernelGGL(k_lu_leaf<kUpper>, dim3(cdiv(c_hi - c_lo, LuTileFlat::BN), d.nmat), dim3(LuTileFlat::NT), 0,
+                         ctx->stream, a, W, r0, rows, c_lo, c_hi);
+    else
+      hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream,
+                         a, r0, rows, c_lo, c_hi);
   }
   // unit lower solve on rows [lo, hi) of columns [c_lo, c_hi)
   void trsm_lower(int lo, int hi, int c_lo, int c_hi) {
@@ -468,7 +550,8 @@ struct LuRun {
   void factor(int c0, int c1) {
     if (c1 - c0 <= W) {
       const int rows = cdiv(d.n - c0, R);
-      const int threads = std::min(LB, std::max(64, cdiv(rows, 64) * 64));
+      // at least four waves: they invert the panel's diagonal block at the end
+      const int threads = std::min(LB, std::max(256, cdiv(rows, 64) * 64));
       KernelScope ks_(ctx, "panel");
       hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
       return;
@@ -496,9 +579,13 @@ ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_solve: order out of range");
   const int W = panel_width(ctx, d.n);
-  if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run();
-  if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run();
-  return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run();
+  LuArgs a = make_args(d);
+  // the panels keep the inverses of their diagonal blocks for the triangular-solve leaves
+  a.sInv = (long)cdiv(d.n, W) * 2 * W * W;
+  SS_TRY(workspace(ctx, kSlotLuInv, sizeof(double2) * (size_t)d.nmat * a.sInv, (void **)&a.inv));
+  if (W == 32) return LuRun<32, 1, 512>{ctx, d, a}.run();
+  if (W == 16) return LuRun<16, 1, 1024>{ctx, d, a}.run();
+  return LuRun<8, 2, 1024>{ctx, d, a}.run();
 }
 
 ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
