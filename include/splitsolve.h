@@ -152,6 +152,17 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
 ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx,
                                 const double *E, int prec, int flags, ss_c128 *Q, int *info);
 
+/* The block solver of Step 1 on its own: batched LU with partial pivoting (Alg. 1 solves every
+ * D_i X_i = A_{i,i+1} through this factorization).
+ *
+ * A [nmat][n][n] (row-major complex128) is overwritten with the factors of P A = L U in LAPACK's getrf
+ * layout: row i holds row i of L (unit lower, strictly below the diagonal) and of U (on and above it)
+ * in the pivoted order.  perm [nmat][n]: row i of P A is row perm[i] of the input.  The pivot of each
+ * column is the entry of largest |Re| + |Im| among the remaining rows, the lowest row on ties (the
+ * rule of LAPACK's izamax).  info [nmat] (may be NULL): 0, or 1 + c for an exactly zero pivot in
+ * column c (elimination continues past it, as getrf does).  1 <= n <= 2048; nmat >= 0. */
+ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int *info);
+
 /* Steps 2-4 (Sec. 3B, Eq. (x)): fold the boundary self-energies in and recover the wave function.
  *
  * With C Q = [Sigma_L Q_{1,:}; Sigma_R Q_{n_B,:}] (2s x 2s), R = I - C Q, b' = inj (the non-zero

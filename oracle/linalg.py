@@ -45,6 +45,36 @@ def btd_solve(diag, upper, lower, rhs):
     return x
 
 
+def lu_partial_pivot(a):
+    """Gaussian elimination with partial pivoting, written out (the block solver of Alg. 1, Sec. 3B).
+
+    Column by column: the pivot is the remaining row with the largest |Re| + |Im| in the column (the
+    lowest such row on ties), it is swapped into place, the entries below it become the multipliers
+    (divided by the pivot) and the trailing block takes the rank-1 update.  An exactly zero pivot is
+    recorded (1 + column, first one only) and its column is skipped.  Returns (lu, perm, info) with lu
+    holding unit-lower L below and U on and above the diagonal of P a = L U, and row i of P a being
+    row perm[i] of a.
+    """
+    lu = np.array(a, dtype=np.complex128, copy=True)
+    n = lu.shape[0]
+    perm = np.arange(n)
+    info = 0
+    for j in range(n):
+        mag = np.abs(lu[j:, j].real) + np.abs(lu[j:, j].imag)
+        p = j + int(np.argmax(mag))  # argmax returns the first maximum
+        if p != j:
+            lu[[j, p]] = lu[[p, j]]
+            perm[[j, p]] = perm[[p, j]]
+        piv = lu[j, j]
+        if piv == 0:
+            if info == 0:
+                info = j + 1
+            continue
+        lu[j + 1:, j] /= piv
+        lu[j + 1:, j + 1:] -= np.outer(lu[j + 1:, j], lu[j, j + 1:])
+    return lu, perm, info
+
+
 def boundary_rhs(nb: int, s: int, top, bottom):
     """Right-hand side whose only non-zero block rows are the first (``top``) and last (``bottom``).
 

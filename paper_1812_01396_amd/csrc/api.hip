@@ -222,6 +222,15 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   return precompute_columns(ctx, hs, batch, kidx, E, prec, flags, Q, info);
 }
 
+ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int *info) {
+  SS_TRY(enter(ctx));
+  if (nmat < 0 || n < 1) return fail(ctx, SS_ERR_ARG, "ss_lu_factor: size out of range");
+  if (n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_lu_factor: n > 2048");
+  if (nmat == 0) return SS_OK;
+  if (!A || !perm) return fail(ctx, SS_ERR_ARG, "ss_lu_factor: null pointer");
+  return lu_factor_dense(ctx, nmat, n, (double2 *)A, perm, info);
+}
+
 ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
                        const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
   SS_TRY(enter(ctx));

@@ -597,6 +597,44 @@ ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run(false);
 }
 
+// rows of every system in the factorization's logical order: dst[i] = src[perm[i]] (n x n, ld n)
+__global__ void k_gather_rows(const double2 *src, double2 *dst, const int *perm, int n) {
+  const long base = (long)blockIdx.y * n * n;
+  const int *p = perm + (long)blockIdx.y * n;
+  const long total = (long)n * n;
+  for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < total; idx += (long)gridDim.x * blockDim.x) {
+    const int r = idx / n, c = idx % n;
+    dst[base + idx] = src[base + (long)p[r] * n + c];
+  }
+}
+
+ss_status lu_factor_dense(ss_ctx *ctx, int nmat, int n, double2 *A, int *perm, int *info) {
+  if (nmat <= 0) return SS_OK;
+  if (n < 1 || n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_factor: order out of range");
+  int *zp = info;
+  if (!zp) SS_TRY(workspace(ctx, kSlotZp, sizeof(int) * (size_t)nmat, (void **)&zp));
+  LuDesc d;
+  d.nmat = nmat;
+  d.n = n;
+  d.nrhs = 0;
+  d.M = A;
+  d.sM = (long)n * n;
+  d.ldm = n;
+  d.perm = perm;
+  d.sP = n;
+  d.zp = zp;
+  SS_TRY(lu_identity_perm(ctx, d));
+  SS_TRY(lu_solve(ctx, d));
+  void *tmp;
+  const size_t bytes = sizeof(double2) * (size_t)nmat * n * n;
+  SS_TRY(workspace(ctx, kSlotM, bytes, &tmp));
+  const int blocks = (int)std::min<long>(((long)n * n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_gather_rows, dim3(blocks, nmat), dim3(256), 0, ctx->stream, A, (double2 *)tmp, perm, n);
+  if (hipMemcpyAsync(A, tmp, bytes, hipMemcpyDeviceToDevice, ctx->stream) != hipSuccess)
+    return fail(ctx, SS_ERR_DEVICE, "lu_factor: copy failed");
+  return check_launch(ctx, "lu_factor");
+}
+
 ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   hipLaunchKernelGGL(k_identity_perm, dim3(cdiv(d.n, 256), d.nmat), dim3(256), 0, ctx->stream, d.perm, d.sP,

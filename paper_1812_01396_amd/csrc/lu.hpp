@@ -46,5 +46,8 @@ ss_status lu_identity_perm(ss_ctx *ctx, const LuDesc &d);
 // Apply factors kept from an earlier lu_solve (M holds L\U in physical rows, perm the row map) to new
 // right-hand sides: X = U^{-1} L^{-1} P RHS (no factorization).
 ss_status lu_apply(ss_ctx *ctx, const LuDesc &d);
+// Factor nmat dense n x n systems in place and return the factors in pivoted row order (getrf layout)
+// with the row map perm and the zero-pivot codes info (may be null).
+ss_status lu_factor_dense(ss_ctx *ctx, int nmat, int n, double2 *A, int *perm, int *info);
 
 }  // namespace ss

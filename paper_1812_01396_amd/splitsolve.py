@@ -24,7 +24,7 @@ SS_KEEP_FACTORS = 1
 EXPORTS = (
     "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_synchronize", "ss_status_string", "ss_last_error",
     "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy",
-    "ss_precompute_columns", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
+    "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
@@ -102,6 +102,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_lead_selfenergy.restype = I
     lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, I, I, P, P]
     lib.ss_precompute_columns.restype = I
+    lib.ss_lu_factor.argtypes = [P, I, I, P, P, P]
+    lib.ss_lu_factor.restype = I
     lib.ss_apply_obc.argtypes = [P, I, I, I, P, P, I, P, P, P, P]
     lib.ss_apply_obc.restype = I
     lib.ss_transmission.argtypes = [P, I, I, P, P, P]
@@ -296,6 +298,23 @@ def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, in
     ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), int(prec),
                                             flags, _ptr(Q), _ptr(info)))
     return Q, info
+
+
+def ss_lu_factor(ctx: Context, A, perm=None, info=None):
+    """Batched LU with partial pivoting, in place (see ss_lu_factor in splitsolve.h).
+
+    A: [nmat, n, n] complex128 (overwritten with L and U of P A = L U, getrf layout).  Returns
+    (A, perm [nmat, n] int32, info [nmat] int32), all on the device.
+    """
+    dev = ctx.device
+    nmat, n, n2 = A.shape
+    _need(A, torch.complex128, dev, "A", (nmat, n, n))
+    perm = perm if perm is not None else torch.empty(nmat, n, dtype=torch.int32, device=dev)
+    info = info if info is not None else torch.empty(nmat, dtype=torch.int32, device=dev)
+    _need(perm, torch.int32, dev, "perm", (nmat, n))
+    _need(info, torch.int32, dev, "info", (nmat,))
+    ctx.check(ctx.lib.ss_lu_factor(ctx.handle, nmat, n, _ptr(A), _ptr(perm), _ptr(info)))
+    return A, perm, info
 
 
 def ss_apply_obc(ctx: Context, Q, sigma, inj=None, psi=None, gc=None, info=None, want_gc: bool = True):

@@ -156,3 +156,37 @@ def test_chain_crystal_all_energies(ctx):
         ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, *cell, Es[b], 1e-8)
         assert _rel(out["q"][b], ref["q"]) <= TOL
         assert abs(out["T"][b, 0] - ref["t_lr"]) <= TOL * max(1.0, ref["t_lr"])
+
+
+@pytest.mark.parametrize("n,nmat", [(1, 2), (33, 3), (100, 2), (512, 3), (700, 2), (1100, 1)])
+def test_lu_factor_vs_oracle(ctx, n, nmat):
+    """The batched LU (panel widths 32, 16 and 8 by order) takes the oracle's pivots exactly and its
+    factors agree element by element (rounding-order differences only)."""
+    import paper_1812_01396_amd as ss
+    print(f"lu_factor n={n} nmat={nmat}", flush=True)
+    rng = np.random.default_rng(n + nmat)
+    a = rng.standard_normal((nmat, n, n)) + 1j * rng.standard_normal((nmat, n, n))
+    lu, perm, info = ss.ss_lu_factor(ctx, _dev(a))
+    torch.cuda.synchronize()
+    lu, perm, info = lu.cpu().numpy(), perm.cpu().numpy(), info.cpu().numpy()
+    for b in range(nmat):
+        ref, rperm, rinfo = linalg.lu_partial_pivot(a[b])
+        assert info[b] == rinfo == 0
+        assert np.array_equal(perm[b], rperm), (b, int(np.argmax(perm[b] != rperm)))
+        assert np.abs(lu[b] - ref).max() <= 1e-11 * np.abs(ref).max(), (b, np.abs(lu[b] - ref).max())
+
+
+def test_lu_factor_zero_pivots(ctx):
+    import paper_1812_01396_amd as ss
+    rng = np.random.default_rng(9)
+    a = rng.standard_normal((2, 40, 40)) + 1j * rng.standard_normal((2, 40, 40))
+    a[0, :, 17] = 0.0  # column 17 is exactly zero after any elimination
+    a[1, :, 39] = 0.0
+    lu, perm, info = ss.ss_lu_factor(ctx, _dev(a))
+    torch.cuda.synchronize()
+    for b in range(2):
+        ref, rperm, rinfo = linalg.lu_partial_pivot(a[b])
+        assert info.cpu().numpy()[b] == rinfo
+        assert np.array_equal(perm.cpu().numpy()[b], rperm)
+        assert np.abs(lu.cpu().numpy()[b] - ref).max() <= 1e-11 * np.abs(ref).max()
+    assert list(info.cpu().numpy()) == [18, 40]

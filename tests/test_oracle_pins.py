@@ -332,3 +332,42 @@ def test_decimation_conditioning_pins():
         if np.max(np.abs(al)) + np.max(np.abs(be)) <= 1e-14 * np.max(np.abs((E + 1j * eta) - eps0)):
             break
     assert est == pytest.approx(worst, rel=1e-8)
+
+
+def _perm_from_ipiv(ipiv):
+    perm = np.arange(len(ipiv))
+    for j, p in enumerate(ipiv):
+        perm[[j, p]] = perm[[p, j]]
+    return perm
+
+
+@pytest.mark.parametrize("n,seed", [(1, 0), (7, 1), (64, 2), (150, 3)])
+def test_lu_partial_pivot_matches_lapack_getrf(n, seed):
+    """The written-out elimination takes LAPACK's pivots (izamax: largest |Re| + |Im|, first on ties)
+    and reproduces its factors and P a = L U."""
+    import scipy.linalg as sla
+    rng = np.random.default_rng(seed)
+    a = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    lu, perm, info = linalg.lu_partial_pivot(a)
+    ref, ipiv = sla.lu_factor(a)
+    assert info == 0
+    assert np.array_equal(perm, _perm_from_ipiv(ipiv))
+    assert np.abs(lu - ref).max() <= 1e-12 * max(1.0, np.abs(ref).max())
+    L = np.tril(lu, -1) + np.eye(n)
+    U = np.triu(lu)
+    assert np.abs(a[perm] - L @ U).max() <= 1e-12 * np.abs(a).max() * n
+
+
+def test_lu_partial_pivot_tie_rule_and_zero_pivot():
+    # column 0: |Re| + |Im| is 2 for rows 1, 2 and 3 (2, 2j, 1+1j): the lowest such row (1) is the pivot
+    a = np.array([[0.5, 1.0, 0.0], [2.0, 0.0, 1.0], [2.0j, 1.0, 0.0], [1.0 + 1.0j, 0.0, 0.0]])[:, :3]
+    a = np.concatenate([a, np.zeros((4, 1))], axis=1)  # 4 x 4 with a zero last column
+    lu, perm, info = linalg.lu_partial_pivot(a)
+    assert perm[0] == 1
+    assert info == 4  # the last column is exactly zero after elimination
+    # a zero column in the middle: recorded, skipped, elimination continues below it
+    b = np.array([[1.0, 0.0, 2.0], [3.0, 0.0, 1.0], [0.5, 0.0, 4.0]], dtype=complex)
+    lu, perm, info = linalg.lu_partial_pivot(b)
+    assert info == 2 and perm[0] == 1
+    L = np.tril(lu, -1) + np.eye(3)
+    assert np.allclose(b[perm], L @ np.triu(lu))
