@@ -39,6 +39,21 @@ __device__ __forceinline__ double2 crecip(double2 u) {
 // keeps register arrays out of registers)
 __device__ __forceinline__ void st2(double2 &dst, double2 v) { dst.x = v.x; dst.y = v.y; }
 __device__ __forceinline__ double2 ld2(const double2 &s) { return make_double2(s.x, s.y); }
+// Lane exchanges inside a row of 16 lanes through DPP (no LDS round trip).  kCtrl: 0xB1 swaps
+// neighbours (lane ^ 1), 0x4E swaps pairs (lane ^ 2), 0x141 mirrors each half-row of 8 (lane i <-> 7 - i),
+// 0x140 mirrors the row (lane i <-> 15 - i).  Every lane of the row must be active.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_int(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, kCtrl, 0xF, 0xF, false);
+}
+template <int kCtrl>
+__device__ __forceinline__ double dpp_double(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = dpp_int<kCtrl>((int)(b & 0xffffffffLL));
+  const int hi = dpp_int<kCtrl>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // LAPACK's pivot magnitude |Re| + |Im|
 __device__ __forceinline__ double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 

@@ -114,10 +114,10 @@ __device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, co
       ax += lx * x[t].x - ly * x[t].y;
       ay += lx * x[t].y + ly * x[t].x;
     }
-    ax += __shfl_xor(ax, 1);
-    ay += __shfl_xor(ay, 1);
-    ax += __shfl_xor(ax, 2);
-    ay += __shfl_xor(ay, 2);
+    ax += dpp_double<0xB1>(ax);
+    ay += dpp_double<0xB1>(ay);
+    ax += dpp_double<0x4E>(ax);
+    ay += dpp_double<0x4E>(ay);
     if (part == (i & 3)) {
       double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
       if (kUpper) v = cmul(v, ld2(rdiag[i]));
@@ -194,12 +194,16 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
         if (t > bv) { bv = t; bi = lr; }
       }
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int oi = __shfl_xor(bi, off);
+    // wave arg-max: DPP exchanges inside each row of 16 lanes, then across rows
+    auto merge = [&](double ov, int oi) {
       if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    }
+    };
+    merge(dpp_double<0xB1>(bv), dpp_int<0xB1>(bi));
+    merge(dpp_double<0x4E>(bv), dpp_int<0x4E>(bi));
+    merge(dpp_double<0x141>(bv), dpp_int<0x141>(bi));
+    merge(dpp_double<0x140>(bv), dpp_int<0x140>(bi));
+    merge(__shfl_xor(bv, 16), __shfl_xor(bi, 16));
+    merge(__shfl_xor(bv, 32), __shfl_xor(bi, 32));
     if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
     __syncthreads();
     bv = red_v[0];
@@ -253,14 +257,36 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
       const double2 v0 = v[q * W];
       const double2 p = cmul(v0, ui);
       const double lx = below ? p.x : v0.x, ly = below ? p.y : v0.y;
+      // multiplier: zero leaves rows on and above the pivot (and rows past the end) unchanged
+      const double mx = below ? p.x : 0.0, my = below ? p.y : 0.0;
+      // position c + 1 holds column j + 1 + c while c < W - 1 - j (later columns); the rest are done and
+      // only move.  The bound is uniform over the workgroup: whole groups of 4 positions branch, only the
+      // group that straddles it selects per position.
+      const int live_pos = W - 1 - j;
 #pragma unroll
-      for (int c = 0; c < W - 1; ++c) {
-        // position c + 1 holds column j + 1 + c while c < W - 1 - j (later columns); the rest are done
-        const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
-        const double vx = v[q * W + c + 1].x, vy = v[q * W + c + 1].y;
-        const bool upd = below && (c < W - 1 - j);
-        v[q * W + c].x = upd ? vx - lx * ux + ly * uy : vx;
-        v[q * W + c].y = upd ? vy - lx * uy - ly * ux : vy;
+      for (int g = 0; g < (W - 1 + 3) / 4; ++g) {
+        if (4 * g + 4 <= live_pos) {
+#pragma unroll
+          for (int c = 4 * g; c < 4 * g + 4 && c < W - 1; ++c) {
+            const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
+            const double vx = v[q * W + c + 1].x, vy = v[q * W + c + 1].y;
+            v[q * W + c].x = vx - mx * ux + my * uy;
+            v[q * W + c].y = vy - mx * uy - my * ux;
+          }
+        } else if (4 * g >= live_pos) {
+#pragma unroll
+          for (int c = 4 * g; c < 4 * g + 4 && c < W - 1; ++c) v[q * W + c] = v[q * W + c + 1];
+        } else {
+#pragma unroll
+          for (int c = 4 * g; c < 4 * g + 4 && c < W - 1; ++c) {
+            const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
+            const double vx = v[q * W + c + 1].x, vy = v[q * W + c + 1].y;
+            const bool upd = c < live_pos;
+            v[q * W + c].x = upd ? vx - mx * ux + my * uy : vx;
+            v[q * W + c].y = upd ? vy - mx * uy - my * ux : vy;
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);  // keep each group's pivot-row loads with the group (registers)
       }
       v[q * W + W - 1].x = lx;
       v[q * W + W - 1].y = ly;
