@@ -394,13 +394,14 @@ __global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm(LuArgs a, int r
   static_assert(T::NT == 256, "load_perm assumes 256 threads");
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sperm[kLuMaxN];
-  const int mat = blockIdx.y;
+  int tile, mat;
+  xcd_tile_order(tile, mat);
   if (skipped(a, mat)) return;
   double2 *M = a.M + (long)mat * a.sM;
   const ColView cv = col_view(a, mat, c_lo);
   load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
   const int tc = cdiv(c_hi - c_lo, T::BN);
-  const int m0 = r_lo + (blockIdx.x / tc) * T::BM, n0 = c_lo + (blockIdx.x % tc) * T::BN;
+  const int m0 = r_lo + (tile / tc) * T::BM, n0 = c_lo + (tile % tc) * T::BN;
   Acc<T> acc;
   acc.zero();
   LdRowPerm la{M, a.ldm, sperm};

@@ -111,11 +111,13 @@ using DecTile = TileCfg<64, 64, 16, 2, 2>;
 __global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_update(DecArgs a, int par) {
   using T = DecTile;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int inst = blockIdx.y, s = a.s;
+  int tile, inst;
+  xcd_tile_order(tile, inst);
+  const int s = a.s;
   if (a.done[inst]) return;
   const long ss2 = (long)s * s;
   const int tiles = cdiv(s, T::BM);
-  const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
+  const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
   const double2 *alpha = dec_mat(a, inst, kAlpha0 + par);
   const double2 *beta = dec_mat(a, inst, kBeta0 + par);
   double2 *alpha_n = dec_mat(a, inst, kAlpha0 + (par ^ 1));

@@ -90,7 +90,9 @@ __global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_
 k_form(SweepArgs a, int t) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
+  int tile, mat;
+  xcd_tile_order(tile, mat);
+  const int inst = mat >> 1, dir = mat & 1;
   const int s = a.s, nb = nb_of(a, inst);
   if (t >= nb) return;
   const int ks = set_of(a, inst);
@@ -102,7 +104,6 @@ k_form(SweepArgs a, int t) {
   double2 *M = a.M + (long)mat * 2 * ss2;
   const int tiles = cdiv(s, T::BM);
   const int ntile = tiles * tiles;
-  int tile = blockIdx.x;
 
   if (tile == 0 && threadIdx.x == 0 && t > 0) {
     const int z = a.zp[mat];
@@ -193,12 +194,14 @@ __global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_
 k_chain(SweepArgs a, int u) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int mat = blockIdx.y, inst = mat >> 1, dir = mat & 1;
+  int tile, mat;
+  xcd_tile_order(tile, mat);
+  const int inst = mat >> 1, dir = mat & 1;
   const int s = a.s, nb = nb_of(a, inst);
   if (u >= nb) return;
   const long ss2 = (long)s * s;
   const int tiles = cdiv(s, T::BM);
-  const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
+  const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
   const int ib = dir == 0 ? u : nb - 1 - u;
   const double2 *x = xslot(a, mat, nb - 1 - u);
   double2 *q0 = a.Q + boff_of(a, inst) * 2 * ss2 + (dir ? s : 0);

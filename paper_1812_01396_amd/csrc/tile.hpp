@@ -55,6 +55,24 @@ struct Acc {
   }
 };
 
+// ------------------------------------------------------------------ XCD-aware tile order
+// Workgroups go to the eight XCDs (each with its own L2) round-robin by linear id.  For a grid of
+// (tiles, systems) this remaps the ids so that every tile of a system runs on one XCD, in tile order,
+// and that XCD's L2 serves the operand panels the tiles share.  A bijection of the grid; grids whose
+// system count is not a multiple of 8 keep the plain order.
+__device__ __forceinline__ void xcd_tile_order(int &tile, int &sys) {
+  const int nt = gridDim.x, ns = gridDim.y;
+  if (ns % 8 != 0) {
+    tile = blockIdx.x;
+    sys = blockIdx.y;
+    return;
+  }
+  const long lin = blockIdx.x + (long)nt * blockIdx.y;
+  const long slot = lin >> 3;
+  sys = (int)(lin & 7) + 8 * (int)(slot / nt);
+  tile = (int)(slot % nt);
+}
+
 // ------------------------------------------------------------------ loaders
 // A loader returns element (r, k) of the left operand, a B loader element (k, c) of the right one.
 // kFastSecond: consecutive values of the second index are contiguous in memory (row-major).
