@@ -49,6 +49,8 @@ WORKLOADS = {
     "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=16),
 }
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
+# kernel families of the first/last-column recursion (Step 1)
+RECURSION_FAMILIES = ",form,chain,panel,lu_gemm,trsm,"
 UNEVEN = dict(n=256, sizes=(128, 256, 384, 512, 768), nb_lo=16, nb_hi=64, e_lo=-5.0, e_hi=5.0, seed=3, eta=1e-8,
               m=32)
 
@@ -482,7 +484,9 @@ class Pipeline:
         self.ctx_s = ss.Context(0, self.stream_sig)
         ss.splitsolve._check_kidx(self.kidx, len(insts))  # once: the step itself never reads back to the host
 
-    def run(self):
+    def run(self, recursion_ms=None):
+        """One step.  recursion_ms: a list that receives the summed duration (ms) of the recursion's
+        kernels of each chunk (HIP events on the main stream; synchronizes after each chunk's recursion)."""
         ss, torch, w = self.ss, self.torch, self.w
         # the previous step's readers of sigma (main stream) finish before sigma is overwritten
         prev = torch.cuda.Event()
@@ -506,9 +510,14 @@ class Pipeline:
         for c0 in range(0, self.n, self.chunk):
             c1 = min(c0 + self.chunk, self.n)
             q = self.Qbuf[: c1 - c0]
+            if recursion_ms is not None:
+                self.ctx.kernel_timer(RECURSION_FAMILIES)
             ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
                                      kidx=self.kidx[c0:c1], Q=q, info=self.info_q[c0:c1], validate=False,
                                      prec=ss.SS_PREC_FP32 if mixed else ss.SS_PREC_FP64, keep_factors=mixed)
+            if recursion_ms is not None:
+                recursion_ms.append(self.ctx.kernel_timer_read()[0])
+                self.ctx.kernel_timer(None)
             if c0 == 0:
                 th.join()
                 if err:
@@ -572,6 +581,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only copy 1 GiB device to device three times (a plain copy of known size, for "
                          "calibrating the FETCH_SIZE and WRITE_SIZE counters)")
+    ap.add_argument("--ceilings", action="store_true",
+                    help="only measure this GPU's FP64/FP32 matrix-core, FP64 vector and copy rates")
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -583,6 +594,14 @@ def main():
 
     import torch
 
+    if args.ceilings:
+        import paper_1812_01396_amd as ss
+        ctx = ss.Context(0)
+        print(json.dumps(dict(ceilings=ctx.measure_ceilings(),
+                              datasheet=dict(fp64_mfma_tflops=FP64_PEAK_TFLOPS, fp32_mfma_tflops=FP32_PEAK_TFLOPS,
+                                             fp64_valu_tflops=78.6, hbm_gbps=8000.0))))
+        ctx.close()
+        return
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")  # 1 GiB
         dst = torch.empty_like(src)
@@ -611,6 +630,10 @@ def main():
     elapsed = time.perf_counter() - t0
     k_ms, k_launches, k_flops, k_bytes = timed_ctx.kernel_timer_read(with_flops=True)
     timed_ctx.kernel_timer(None)
+    # one more (untimed) step with the recursion's kernels bracketed by HIP events: recursion TFLOP/s
+    rec_ms = []
+    pipe.run(recursion_ms=rec_ms)
+    torch.cuda.synchronize()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
     mixed = args.mode == "mixed"
@@ -675,6 +698,12 @@ def main():
         "fp64_fallback_per_step": (pipe.fallback / (args.steps + args.warmup) if mixed else None),
         "injection_rank": ([int(pipe.rank.min()), int(pipe.rank.max())] if mixed else None),
         "roofline": roof,
+        # the recursion's algorithmic flops / the summed duration of its kernels (form, chain, LU) in one
+        # step, measured with HIP events while the self-energies run beside it on the second stream
+        "recursion": dict(kernel_ms=round(sum(rec_ms), 2),
+                          tflops=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
+                          frac_peak=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /
+                                          (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4)),
         "cpu_baseline": cpu,
         "t_err_vs_oracle": t_err,
     }

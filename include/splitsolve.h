@@ -79,7 +79,8 @@ size_t ss_workspace_bytes(const ss_ctx *ctx);
 
 /* Kernel timing probe (a profiling aid).  ss_kernel_timer(ctx, family) waits for the stream, clears
  * the accumulated time and from then on brackets every launch of that kernel family on this context
- * with a pair of HIP events on the context's stream (NULL or "" switches the probe off).
+ * with a pair of HIP events on the context's stream (NULL or "" switches the probe off; a list of
+ * families enclosed in commas, such as ",form,chain,", times all of them).
  * ss_kernel_timer_read waits for the stream and returns the summed event time in milliseconds, the
  * number of timed launches, (flops, may be NULL) the algorithmic flops of those launches where the
  * launch site states them (8 m n k per complex product; "lu_gemm" only, else 0) and (bytes, may be
@@ -90,6 +91,12 @@ size_t ss_workspace_bytes(const ss_ctx *ctx);
  * triangular-solve products), "trsm" (triangular-solve leaves), "dec_update" (decimation pass
  * products), "obc" (corner system and psi products), "trans" (transmission). */
 ss_status ss_kernel_timer(ss_ctx *ctx, const char *family);
+/* Measured ceilings of this GPU (a profiling aid, the denominators the roofline fractions are checked
+ * against): ceil (HOST pointer, 4 doubles) receives the FP64 matrix-core rate (TFLOP/s,
+ * v_mfma_f64_16x16x4 on independent accumulators), the FP32 matrix-core rate (v_mfma_f32_16x16x4), the
+ * FP64 vector FMA rate (TFLOP/s) and the rate of a 512 MiB device copy (GB/s, bytes read + written).
+ * Waits for the stream; uses and overwrites the context's workspace (~1 GiB). */
+ss_status ss_measure_ceilings(ss_ctx *ctx, double *ceil);
 ss_status ss_kernel_timer_read(ss_ctx *ctx, double *total_ms, long long *launches, double *flops,
                                double *bytes);
 

@@ -20,7 +20,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsplitsolve.so")
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "lu.hip", "sweep.hip", "selfenergy.hip", "obc.hip", "refine.hip", "plan.hip", "mlp.hip", "warm.hip"]
+SOURCES = ["api.hip", "lu.hip", "sweep.hip", "selfenergy.hip", "obc.hip", "refine.hip", "plan.hip", "mlp.hip", "warm.hip",
+           "ceilings.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

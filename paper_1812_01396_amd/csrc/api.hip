@@ -64,7 +64,10 @@ static hipEvent_t timer_event(ss_ctx *ctx) {
 }
 
 KernelScope::KernelScope(ss_ctx *c, const char *family, double flops, double bytes) : ctx(c), on(false) {
-  if (!ctx->timer_family.empty() && ctx->timer_family == family) {
+  const std::string &tf = ctx->timer_family;
+  const bool match = !tf.empty() && (tf == family || (tf[0] == ',' && tf.find(std::string(",") + family + ",") !=
+                                                                           std::string::npos));
+  if (match) {
     hipEvent_t e = timer_event(ctx);
     if (e && hipEventRecord(e, ctx->stream) == hipSuccess) {
       on = true;
@@ -220,6 +223,13 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   if (flags & ~SS_KEEP_FACTORS) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown flags");
   ctx->corner_valid = false;  // the recursion reuses the corner system's workspace
   return precompute_columns(ctx, hs, batch, kidx, E, prec, flags, Q, info);
+}
+
+ss_status ss_measure_ceilings(ss_ctx *ctx, double *ceil) {
+  SS_TRY(enter(ctx));
+  if (!ceil) return fail(ctx, SS_ERR_ARG, "ss_measure_ceilings: null output");
+  if (ctx->sync_free) return fail(ctx, SS_ERR_ARG, "ss_measure_ceilings: not in sync-free mode");
+  return measure_ceilings(ctx, ceil);
 }
 
 ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int *info) {

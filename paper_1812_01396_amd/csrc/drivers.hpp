@@ -68,4 +68,7 @@ ss_status sigma_decode(ss_ctx *ctx, int n, int s, const float *y, const float *m
 ss_status transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
                            double *T);
 
+// Rates of plain MFMA, vector-FMA and copy kernels (see ss_measure_ceilings).
+ss_status measure_ceilings(ss_ctx *ctx, double *ceil);
+
 }  // namespace ss

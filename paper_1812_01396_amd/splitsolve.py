@@ -23,7 +23,7 @@ SS_KEEP_FACTORS = 1
 
 EXPORTS = (
     "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_synchronize", "ss_status_string", "ss_last_error",
-    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_lead_selfenergy",
+    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
@@ -93,6 +93,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_last_error.restype = ctypes.c_char_p
     lib.ss_workspace_bytes.argtypes = [P]
     lib.ss_workspace_bytes.restype = Z
+    lib.ss_measure_ceilings.argtypes = [P, ctypes.POINTER(D)]
+    lib.ss_measure_ceilings.restype = I
     lib.ss_kernel_timer.argtypes = [P, ctypes.c_char_p]
     lib.ss_kernel_timer.restype = I
     lib.ss_kernel_timer_read.argtypes = [P, ctypes.POINTER(D), ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(D),
@@ -218,6 +220,12 @@ class Context:
 
     def workspace_bytes(self) -> int:
         return int(self.lib.ss_workspace_bytes(self.handle))
+
+    def measure_ceilings(self) -> dict:
+        """Measured FP64/FP32 matrix-core, FP64 vector and copy rates of this GPU (ss_measure_ceilings)."""
+        out = (ctypes.c_double * 4)()
+        self.check(self.lib.ss_measure_ceilings(self.handle, out))
+        return dict(fp64_mfma_tflops=out[0], fp32_mfma_tflops=out[1], fp64_valu_tflops=out[2], copy_gbps=out[3])
 
     def kernel_timer(self, family: str | None):
         """Start (or with None stop) bracketing launches of one kernel family with HIP events."""
