@@ -12,6 +12,9 @@
 #include <cmath>
 #include <map>
 #include <numeric>
+#include <string>
+#include <thread>
+#include <vector>
 
 #include "drivers.hpp"
 #include "lu.hpp"
@@ -216,29 +219,62 @@ ss_status run_chunk(ss_plan *p, Group &g, const Chunk &c) {
   return check_launch(x, "ss_plan: scatter");
 }
 
-ss_status run_group(ss_plan *p, Group &g) {
+// Enqueue a group's chunks; on failure `msg` names the group and the error (p->ctx is not touched, so
+// groups may enqueue from different host threads).
+ss_status enqueue_group(ss_plan *p, Group &g, std::string &msg) {
   for (const Chunk &c : g.chunks) {
     ss_status st = run_chunk(p, g, c);
-    if (st != SS_OK) return fail(p->ctx, st, "group s=" + std::to_string(g.s) + ": " + g.ctx->err);
+    if (st != SS_OK) {
+      msg = "group s=" + std::to_string(g.s) + ": " + g.ctx->err;
+      return st;
+    }
   }
   return SS_OK;
 }
 
+ss_status run_group(ss_plan *p, Group &g) {
+  std::string msg;
+  const ss_status st = enqueue_group(p, g, msg);
+  return st == SS_OK ? SS_OK : fail(p->ctx, st, msg);
+}
+
 // Enqueue the whole batch on `origin`: every group forks from it and joins back into it.  With graphs,
-// each group's work is one launch of its captured graph on its stream.
+// each group's work is one launch of its captured graph on its stream.  Without, each group enqueues
+// its launches from a host thread of its own: a launch blocks the enqueuing thread while the stream's
+// hardware queue is full, so one thread enqueuing group after group would keep every group but the
+// current one idle (the groups would run one after the other).
 ss_status enqueue(ss_plan *p, hipStream_t origin) {
   if (hipEventRecord(p->start, origin) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: event record failed");
-  for (Group &g : p->groups) {
+  for (Group &g : p->groups)
     if (hipStreamWaitEvent(g.stream, p->start, 0) != hipSuccess)
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: stream wait failed");
-    if (p->graphs) {
+  if (p->graphs) {
+    for (Group &g : p->groups)
       if (hipGraphLaunch(g.exec, g.stream) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: graph launch failed");
-    } else {
-      SS_TRY(run_group(p, g));
-    }
+  } else if (p->groups.size() == 1) {
+    SS_TRY(run_group(p, p->groups[0]));
+  } else {
+    const size_t ng = p->groups.size();
+    std::vector<ss_status> st(ng, SS_OK);
+    std::vector<std::string> msg(ng);
+    std::vector<std::thread> th;
+    th.reserve(ng);
+    for (size_t i = 0; i < ng; ++i)
+      th.emplace_back([p, i, &st, &msg] {
+        if (hipSetDevice(p->device) != hipSuccess) {
+          st[i] = SS_ERR_DEVICE;
+          msg[i] = "hipSetDevice failed in an enqueue thread";
+          return;
+        }
+        st[i] = enqueue_group(p, p->groups[i], msg[i]);
+      });
+    for (std::thread &t : th) t.join();
+    for (size_t i = 0; i < ng; ++i)
+      if (st[i] != SS_OK) return fail(p->ctx, st[i], msg[i]);
+  }
+  for (Group &g : p->groups)
     if (hipEventRecord(g.done, g.stream) != hipSuccess || hipStreamWaitEvent(origin, g.done, 0) != hipSuccess)
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: join failed");
-  }
   return SS_OK;
 }
 
