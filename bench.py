@@ -171,7 +171,7 @@ class UnevenPipeline:
     """The uneven batch as one ss_plan: crystal devices (every block a copy of the instance's own cell,
     materialised on the GPU), psi for m columns per instance; run() is one plan execution."""
 
-    def __init__(self, n: int = UNEVEN["n"], use_graph: bool = True, autotune: bool = True, mem_gib: float = 96.0):
+    def __init__(self, n: int = UNEVEN["n"], use_graph: bool = True, autotune: bool = True, mem_gib: float = 0.0):
         import torch
 
         import paper_1812_01396_amd as ss
@@ -198,6 +198,10 @@ class UnevenPipeline:
         print(f"uneven256: inputs resident ({time.perf_counter() - t0:.0f} s); creating the plan", file=sys.stderr,
               flush=True)
         t0 = time.perf_counter()
+        if mem_gib <= 0:  # the device memory left after the inputs, less a margin
+            free, _ = torch.cuda.mem_get_info(dev)
+            mem_gib = max(8.0, free / (1 << 30) - 4.0)
+        self.mem_gib = mem_gib
         self.plan = ss.Plan(self.ctx, self.instances, self.w["eta"], m=m, use_graph=use_graph, autotune=autotune,
                             mem_bytes=int(mem_gib * (1 << 30)))
         torch.cuda.synchronize()
@@ -272,7 +276,7 @@ def run_uneven(args):
         "data": "synthetic",
         "config": {"workload": "uneven256", "instances": len(pipe.specs), "sizes": list(UNEVEN["sizes"]),
                    "nb_range": [UNEVEN["nb_lo"], UNEVEN["nb_hi"]], "m_inj": m, "eta": UNEVEN["eta"],
-                   "graph": not args.no_graph, "autotune": not args.no_autotune, "plan_mem_gib": args.plan_mem_gib,
+                   "graph": not args.no_graph, "autotune": not args.no_autotune, "plan_mem_gib": round(pipe.mem_gib, 1),
                    "precision": "fp64"},
         "tflops_step": round(achieved, 3),
         "sweep_tflop": round(f_sweep / 1e12, 2),
@@ -573,7 +577,8 @@ def main():
     ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS) + ["uneven256", "learned"])
     ap.add_argument("--no-graph", action="store_true", help="uneven256: enqueue eagerly instead of a graph replay")
     ap.add_argument("--no-autotune", action="store_true", help="uneven256: default panel widths and chunks")
-    ap.add_argument("--plan-mem-gib", type=float, default=96.0, help="uneven256: chunk work memory")
+    ap.add_argument("--plan-mem-gib", type=float, default=0.0,
+                    help="uneven256: chunk work memory (0: the device memory left after the inputs, less 4 GiB)")
     ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
     ap.add_argument("--roofline-kernel", default="lu_gemm",
