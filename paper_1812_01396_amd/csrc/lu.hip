@@ -506,6 +506,78 @@ __global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs
   });
 }
 
+// Operand element (r, c) of a row-major array (in LDS or global memory) whose column 0 is column c0.
+struct LdPlain {
+  const double2 *p;
+  int ld, c0;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int c) const { return p[r * ld + (c - c0)]; }
+};
+
+using LuTileHalf = TileCfg<32, 64, 16, 1, 4>;
+
+// 64-row leaf of the right-hand-side solves from two 32-column panels, in place, for 64 columns:
+//   unit lower:  X1 = A^{-1} C1,  X2 = B^{-1} (C2 - L21 X1)
+//   upper:       X2 = B^{-1} C2,  X1 = A^{-1} (C1 - U12 X2)
+// with A^{-1}, B^{-1} the panels' inverses of their diagonal blocks (rows r0 and r0 + 32) and the
+// coupling block read from the factors.  The three products run on the matrix cores; the first
+// half's result and the updated second half pass through LDS.  Requires W = 32 and r0 + 64 <= n.
+template <bool kUpper>
+__global__ void __launch_bounds__(LuTileHalf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int c_lo, int c_hi) {
+  using T = LuTileHalf;
+  constexpr int H = 32, BP = T::BN + 1;
+  __shared__ double lds[T::LDS_DOUBLES];
+  __shared__ double2 buf[H][BP];
+  __shared__ int sp[2 * H];
+  const int mat = blockIdx.y;
+  if (skipped(a, mat)) return;
+  const ColView cv = col_view(a, mat, c_lo);
+  double2 *M = a.M + (long)mat * a.sM;
+  if (threadIdx.x < 2 * H) sp[threadIdx.x] = a.perm[(long)mat * a.sP + r0 + threadIdx.x];
+  __syncthreads();
+  const int n0 = c_lo + blockIdx.x * T::BN;
+  const double2 *inv = a.inv + (long)mat * a.sInv;
+  const int kind = kUpper ? 1 : 0;
+  // first half solved: rows [0, 32) (lower) or [32, 64) (upper) of the block
+  const int f = kUpper ? H : 0, g = kUpper ? 0 : H;
+  const double2 *inv_f = inv + ((long)(r0 + f) / H * 2 + kind) * H * H;
+  const double2 *inv_g = inv + ((long)(r0 + g) / H * 2 + kind) * H * H;
+  {
+    Acc<T> acc;
+    acc.zero();
+    mma_loop<T>(LdPlain{inv_f, H, 0}, LdRowPerm{cv.p, cv.ld, sp + f}, 0, H, n0, c_hi, 0, H, acc, lds);
+    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+      const int gc = n0 + c;
+      st2(buf[r][c], v);
+      if (gc < c_hi) cv.p[(long)sp[f + r] * cv.ld + gc] = v;
+    });
+  }
+  __syncthreads();
+  {
+    // second half: C_g - coupling X_f, coupling = L21 (rows 32.., columns r0..) or U12 (rows 0..31,
+    // columns r0+32..), read through the row map
+    Acc<T> acc;
+    acc.zero();
+    mma_loop<T>(LdRowPerm{M + r0 + f, a.ldm, sp + g}, LdPlain{&buf[0][0], BP, n0}, 0, H, n0, c_hi, 0, H, acc, lds);
+    __syncthreads();  // every wave has read buf
+    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+      const int gc = n0 + c;
+      const double2 cg = gc < c_hi ? cv.p[(long)sp[g + r] * cv.ld + gc] : make_double2(0.0, 0.0);
+      st2(buf[r][c], csub(cg, v));
+    });
+  }
+  __syncthreads();
+  {
+    Acc<T> acc;
+    acc.zero();
+    mma_loop<T>(LdPlain{inv_g, H, 0}, LdPlain{&buf[0][0], BP, n0}, 0, H, n0, c_hi, 0, H, acc, lds);
+    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+      const int gc = n0 + c;
+      if (gc < c_hi) cv.p[(long)sp[g + r] * cv.ld + gc] = v;
+    });
+  }
+}
+
 // X[r][c] = M[perm[r]][n + c]: the solution rows in natural order
 __global__ void k_copy_out(LuArgs a) {
   const int mat = blockIdx.y;
@@ -558,9 +630,23 @@ struct LuRun {
       hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream,
                          a, r0, rows, c_lo, c_hi);
   }
+  // a full 64-row block of two 32-column panels: one fused leaf (three matrix-core products)
+  bool leaf64(bool upper, int lo, int hi, int c_lo, int c_hi) {
+    if (W != 32 || a.inv == nullptr || hi - lo != 64 || lo % 32 != 0) return false;
+    if (c_lo < c_hi) {
+      KernelScope ks_(ctx, "trsm");
+      const dim3 grid(cdiv(c_hi - c_lo, LuTileHalf::BN), d.nmat);
+      if (upper)
+        hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileHalf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
+      else
+        hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileHalf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
+    }
+    return true;
+  }
   // unit lower solve on rows [lo, hi) of columns [c_lo, c_hi)
   void trsm_lower(int lo, int hi, int c_lo, int c_hi) {
     if (hi - lo <= TL) return leaf<false>(lo, hi - lo, c_lo, c_hi);
+    if (leaf64(false, lo, hi, c_lo, c_hi)) return;
     const int m = mid(lo, hi);
     trsm_lower(lo, m, c_lo, c_hi);
     gemm(m, hi, c_lo, c_hi, lo, m);
@@ -569,6 +655,7 @@ struct LuRun {
   // upper solve on rows [lo, hi) of columns [c_lo, c_hi)
   void trsm_upper(int lo, int hi, int c_lo, int c_hi) {
     if (hi - lo <= TL) return leaf<true>(lo, hi - lo, c_lo, c_hi);
+    if (leaf64(true, lo, hi, c_lo, c_hi)) return;
     const int m = mid(lo, hi);
     trsm_upper(m, hi, c_lo, c_hi);
     gemm(lo, m, c_lo, c_hi, m, hi);
