@@ -506,76 +506,100 @@ __global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs
   });
 }
 
-// Operand element (r, c) of a row-major array (in LDS or global memory) whose column 0 is column c0.
-struct LdPlain {
-  const double2 *p;
-  int ld, c0;
-  static constexpr bool kFastSecond = true;
-  __device__ __forceinline__ double2 operator()(int r, int c) const { return p[r * ld + (c - c0)]; }
-};
-
-using LuTileHalf = TileCfg<32, 64, 16, 1, 4>;
-
-// 64-row leaf of the right-hand-side solves from two 32-column panels, in place, for 64 columns:
+// 64-row leaf of the right-hand-side solves from two 32-column panels, in place, for 32 columns:
 //   unit lower:  X1 = A^{-1} C1,  X2 = B^{-1} (C2 - L21 X1)
 //   upper:       X2 = B^{-1} C2,  X1 = A^{-1} (C1 - U12 X2)
 // with A^{-1}, B^{-1} the panels' inverses of their diagonal blocks (rows r0 and r0 + 32) and the
-// coupling block read from the factors.  The three products run on the matrix cores; the first
-// half's result and the updated second half pass through LDS.  Requires W = 32 and r0 + 64 <= n.
+// coupling block read from the factors.  Each of the three 32 x 32 x 32 products stages both operands
+// in LDS once (four waves, one 16 x 16 block each, on the matrix cores); the first result and the
+// updated second half stay in LDS as the next product's right operand.  Requires W = 32, r0 + 64 <= n.
+using LuTileLeaf = TileCfg<32, 32, 32, 2, 2>;
+
 template <bool kUpper>
-__global__ void __launch_bounds__(LuTileHalf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int c_lo, int c_hi) {
-  using T = LuTileHalf;
-  constexpr int H = 32, BP = T::BN + 1;
+__global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int c_lo, int c_hi) {
+  using T = LuTileLeaf;
+  constexpr int H = 32;
+  static_assert(T::BM == H && T::BN == H && T::BK == H && T::NT == 256, "leaf tile");
   __shared__ double lds[T::LDS_DOUBLES];
-  __shared__ double2 buf[H][BP];
   __shared__ int sp[2 * H];
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   const ColView cv = col_view(a, mat, c_lo);
-  double2 *M = a.M + (long)mat * a.sM;
-  if (threadIdx.x < 2 * H) sp[threadIdx.x] = a.perm[(long)mat * a.sP + r0 + threadIdx.x];
+  const double2 *M = a.M + (long)mat * a.sM;
+  const int tid = threadIdx.x;
+  if (tid < 2 * H) sp[tid] = a.perm[(long)mat * a.sP + r0 + tid];
   __syncthreads();
-  const int n0 = c_lo + blockIdx.x * T::BN;
+  const int n0 = c_lo + blockIdx.x * H;
   const double2 *inv = a.inv + (long)mat * a.sInv;
   const int kind = kUpper ? 1 : 0;
-  // first half solved: rows [0, 32) (lower) or [32, 64) (upper) of the block
-  const int f = kUpper ? H : 0, g = kUpper ? 0 : H;
+  const int f = kUpper ? H : 0, g = kUpper ? 0 : H;  // the half solved first, and the other
   const double2 *inv_f = inv + ((long)(r0 + f) / H * 2 + kind) * H * H;
   const double2 *inv_g = inv + ((long)(r0 + g) / H * 2 + kind) * H * H;
-  {
+  Lds<T> L(lds);
+  constexpr int E = H * H / T::NT;  // elements per thread of a 32 x 32 operand
+  // A operand (r, k) -> planes [k][r];  B operand (k, c) -> planes [k][c]
+  auto stage_a = [&](auto load) {
+    double2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) v[e] = load((tid + e * T::NT) / H, (tid + e * T::NT) % H);
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int r = (tid + e * T::NT) / H, k = (tid + e * T::NT) % H;
+      L.ar[k * T::PA + r] = v[e].x;
+      L.ai[k * T::PA + r] = v[e].y;
+    }
+  };
+  auto stage_b = [&](const double2 *v) {
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
+      L.br[k * T::PB + c] = v[e].x;
+      L.bi[k * T::PB + c] = v[e].y;
+    }
+  };
+  auto rows_of = [&](int half, double2 *v) {  // 32 rows of the right-hand side (columns n0..n0+31)
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
+      v[e] = n0 + c < c_hi ? cv.p[(long)sp[half + k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+    }
+  };
+  auto product = [&]() {
     Acc<T> acc;
     acc.zero();
-    mma_loop<T>(LdPlain{inv_f, H, 0}, LdRowPerm{cv.p, cv.ld, sp + f}, 0, H, n0, c_hi, 0, H, acc, lds);
-    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
-      const int gc = n0 + c;
-      st2(buf[r][c], v);
-      if (gc < c_hi) cv.p[(long)sp[f + r] * cv.ld + gc] = v;
-    });
-  }
+    mma_stage<T>(L, acc);
+    return acc;
+  };
+  double2 v[E];
+  // ---- X_f = inv_f C_f
+  rows_of(f, v);
+  stage_a([&](int r, int k) { return inv_f[r * H + k]; });
+  stage_b(v);
   __syncthreads();
-  {
-    // second half: C_g - coupling X_f, coupling = L21 (rows 32.., columns r0..) or U12 (rows 0..31,
-    // columns r0+32..), read through the row map
-    Acc<T> acc;
-    acc.zero();
-    mma_loop<T>(LdRowPerm{M + r0 + f, a.ldm, sp + g}, LdPlain{&buf[0][0], BP, n0}, 0, H, n0, c_hi, 0, H, acc, lds);
-    __syncthreads();  // every wave has read buf
-    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
-      const int gc = n0 + c;
-      const double2 cg = gc < c_hi ? cv.p[(long)sp[g + r] * cv.ld + gc] : make_double2(0.0, 0.0);
-      st2(buf[r][c], csub(cg, v));
-    });
-  }
+  Acc<T> acc = product();
+  __syncthreads();  // operands consumed
+  acc_foreach<T>(acc, [&](int r, int c, double2 x) {
+    if (n0 + c < c_hi) cv.p[(long)sp[f + r] * cv.ld + n0 + c] = x;
+    L.br[r * T::PB + c] = x.x;  // X_f is the next product's right operand
+    L.bi[r * T::PB + c] = x.y;
+  });
+  // ---- Y = C_g - coupling X_f   (coupling: L21 below the first half, U12 right of the second)
+  stage_a([&](int r, int k) { return M[(long)sp[g + r] * a.ldm + r0 + f + k]; });
   __syncthreads();
-  {
-    Acc<T> acc;
-    acc.zero();
-    mma_loop<T>(LdPlain{inv_g, H, 0}, LdPlain{&buf[0][0], BP, n0}, 0, H, n0, c_hi, 0, H, acc, lds);
-    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
-      const int gc = n0 + c;
-      if (gc < c_hi) cv.p[(long)sp[g + r] * cv.ld + gc] = v;
-    });
-  }
+  acc = product();
+  __syncthreads();
+  acc_foreach<T>(acc, [&](int r, int c, double2 x) {  // Y is the last product's right operand
+    const double2 cg = n0 + c < c_hi ? cv.p[(long)sp[g + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+    L.br[r * T::PB + c] = cg.x - x.x;
+    L.bi[r * T::PB + c] = cg.y - x.y;
+  });
+  // ---- X_g = inv_g Y
+  stage_a([&](int r, int k) { return inv_g[r * H + k]; });
+  __syncthreads();
+  acc = product();
+  acc_foreach<T>(acc, [&](int r, int c, double2 x) {
+    if (n0 + c < c_hi) cv.p[(long)sp[g + r] * cv.ld + n0 + c] = x;
+  });
 }
 
 // X[r][c] = M[perm[r]][n + c]: the solution rows in natural order
@@ -635,11 +659,11 @@ struct LuRun {
     if (W != 32 || a.inv == nullptr || hi - lo != 64 || lo % 32 != 0) return false;
     if (c_lo < c_hi) {
       KernelScope ks_(ctx, "trsm");
-      const dim3 grid(cdiv(c_hi - c_lo, LuTileHalf::BN), d.nmat);
+      const dim3 grid(cdiv(c_hi - c_lo, LuTileLeaf::BN), d.nmat);
       if (upper)
-        hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileHalf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
+        hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
       else
-        hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileHalf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
+        hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
     }
     return true;
   }
