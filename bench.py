@@ -46,7 +46,7 @@ WORKLOADS = {
     "dft512": dict(s=512, nb=40, n_e=64, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8],
                    seed=1, eta=1e-8, m=32, chunk=256),
     "chain16": dict(s=16, nb=32, n_e=64, e_lo=-3.0, e_hi=3.0, ks=[0.0], seed=0, eta=1e-8, m=4, chunk=64),
-    "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=16),
+    "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=32),
 }
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
 # kernel families of the first/last-column recursion (Step 1)
@@ -540,6 +540,26 @@ class Pipeline:
                 ss.ss_transmission_psi(self.ctx, self.psi[c0:c1], sig, T=self.T_psi[c0:c1])
             ss.ss_transmission(self.ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
 
+    def recursion_alone(self):
+        """Step 1 by itself (no self-energies beside it): wall time (ms) of ss_precompute_columns over
+        all instances, and the summed duration of its kernels (HIP events)."""
+        ss, torch = self.ss, self.torch
+        mixed = self.mode == "mixed"
+        torch.cuda.synchronize()
+        self.ctx.kernel_timer(RECURSION_FAMILIES)
+        t0 = time.perf_counter()
+        for c0 in range(0, self.n, self.chunk):
+            c1 = min(c0 + self.chunk, self.n)
+            ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
+                                     kidx=self.kidx[c0:c1], Q=self.Qbuf[: c1 - c0], info=self.info_q[c0:c1],
+                                     validate=False, prec=ss.SS_PREC_FP32 if mixed else ss.SS_PREC_FP64,
+                                     keep_factors=mixed)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3
+        kms = self.ctx.kernel_timer_read()[0]
+        self.ctx.kernel_timer(None)
+        return wall, kms
+
     def _fp64_fallback(self, c0, c1):
         """Instances whose refinement from the FP32-product factors did not reach the tolerance (pivot
         blocks too ill-conditioned for FP32 products) are solved again with FP64 products and refined."""
@@ -639,6 +659,7 @@ def main():
     rec_ms = []
     pipe.run(recursion_ms=rec_ms)
     torch.cuda.synchronize()
+    rec_alone_wall, rec_alone_kms = pipe.recursion_alone()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
     mixed = args.mode == "mixed"
@@ -708,7 +729,12 @@ def main():
         "recursion": dict(kernel_ms=round(sum(rec_ms), 2),
                           tflops=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
                           frac_peak=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /
-                                          (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4)),
+                                          (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4),
+                          # Step 1 run by itself after the timed steps (nothing beside it on the chip)
+                          alone_wall_ms=round(rec_alone_wall, 2), alone_kernel_ms=round(rec_alone_kms, 2),
+                          alone_tflops=round(nbatch * sweep_flops(nb, s) / (rec_alone_wall * 1e-3) / 1e12, 3),
+                          alone_frac_peak=round(nbatch * sweep_flops(nb, s) / (rec_alone_wall * 1e-3) / 1e12 /
+                                                (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4)),
         "cpu_baseline": cpu,
         "t_err_vs_oracle": t_err,
     }
