@@ -506,28 +506,35 @@ __global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs
   });
 }
 
-// 64-row leaf of the right-hand-side solves from two 32-column panels, in place, for 32 columns:
+// 64-row leaf of the triangular solves from two 32-column panels, in place, for 32 columns:
 //   unit lower:  X1 = A^{-1} C1,  X2 = B^{-1} (C2 - L21 X1)
 //   upper:       X2 = B^{-1} C2,  X1 = A^{-1} (C1 - U12 X2)
 // with A^{-1}, B^{-1} the panels' inverses of their diagonal blocks (rows r0 and r0 + 32) and the
-// coupling block read from the factors.  Each of the three 32 x 32 x 32 products stages both operands
-// in LDS once (four waves, one 16 x 16 block each, on the matrix cores); the first result and the
-// updated second half stay in LDS as the next product's right operand.  Requires W = 32, r0 + 64 <= n.
+// coupling block read from the factors.  With p0 >= 0 the block first takes the update from the
+// 64-row block already solved at rows p0 (C -= F X_p, F the factors' block at rows r0, columns p0),
+// so the 64-deep product between two such leaves needs no launch (and no pass over C) of its own.
+// Each 32 x 32 x 32 product stages both operands in LDS once (four waves, one 16 x 16 block each, on
+// the matrix cores); partial results stay in the accumulators or in LDS.  Requires W = 32, r0 + 64 <= n.
 using LuTileLeaf = TileCfg<32, 32, 32, 2, 2>;
 
 template <bool kUpper>
-__global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int c_lo, int c_hi) {
+__global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int p0, int c_lo,
+                                                                             int c_hi) {
   using T = LuTileLeaf;
   constexpr int H = 32;
   static_assert(T::BM == H && T::BN == H && T::BK == H && T::NT == 256, "leaf tile");
   __shared__ double lds[T::LDS_DOUBLES];
-  __shared__ int sp[2 * H];
+  __shared__ int sp[2 * H], spp[2 * H];
   const int mat = blockIdx.y;
   if (skipped(a, mat)) return;
   const ColView cv = col_view(a, mat, c_lo);
   const double2 *M = a.M + (long)mat * a.sM;
   const int tid = threadIdx.x;
-  if (tid < 2 * H) sp[tid] = a.perm[(long)mat * a.sP + r0 + tid];
+  const int *perm = a.perm + (long)mat * a.sP;
+  if (tid < 2 * H) {
+    sp[tid] = perm[r0 + tid];
+    if (p0 >= 0) spp[tid] = perm[p0 + tid];
+  }
   __syncthreads();
   const int n0 = c_lo + blockIdx.x * H;
   const double2 *inv = a.inv + (long)mat * a.sInv;
@@ -549,7 +556,13 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
       L.ai[k * T::PA + r] = v[e].y;
     }
   };
-  auto stage_b = [&](const double2 *v) {
+  auto stage_b_rows = [&](const int *rowmap) {  // 32 right-hand-side rows (columns n0..n0+31)
+    double2 v[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
+      v[e] = n0 + c < c_hi ? cv.p[(long)rowmap[k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+    }
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
@@ -557,46 +570,57 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
       L.bi[k * T::PB + c] = v[e].y;
     }
   };
-  auto rows_of = [&](int half, double2 *v) {  // 32 rows of the right-hand side (columns n0..n0+31)
-#pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
-      v[e] = n0 + c < c_hi ? cv.p[(long)sp[half + k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+  // B planes <- C_half - acc (C read from memory in the accumulator's element order)
+  auto publish_diff = [&](const Acc<T> &acc, int half) {
+    acc_foreach<T>(acc, [&](int r, int c, double2 x) {
+      const double2 ch = n0 + c < c_hi ? cv.p[(long)sp[half + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+      L.br[r * T::PB + c] = ch.x - x.x;
+      L.bi[r * T::PB + c] = ch.y - x.y;
+    });
+  };
+  auto coupling = [&](int half, int col0) {  // factors' block at rows r0 + half, columns col0
+    return [=](int r, int k) { return M[(long)sp[half + r] * a.ldm + col0 + k]; };
+  };
+  Acc<T> acc_f, acc_g;
+  acc_f.zero();
+  acc_g.zero();
+  if (p0 >= 0) {  // F X_p for both halves, in two 32-deep steps
+    for (int kk = 0; kk < 2; ++kk) {
+      stage_b_rows(spp + kk * H);
+      stage_a(coupling(f, p0 + kk * H));
+      __syncthreads();
+      mma_stage<T>(L, acc_f);
+      __syncthreads();
+      stage_a(coupling(g, p0 + kk * H));
+      __syncthreads();
+      mma_stage<T>(L, acc_g);
+      __syncthreads();
     }
-  };
-  auto product = [&]() {
-    Acc<T> acc;
-    acc.zero();
-    mma_stage<T>(L, acc);
-    return acc;
-  };
-  double2 v[E];
-  // ---- X_f = inv_f C_f
-  rows_of(f, v);
+  }
+  // ---- X_f = inv_f (C_f - acc_f)
+  publish_diff(acc_f, f);
   stage_a([&](int r, int k) { return inv_f[r * H + k]; });
-  stage_b(v);
   __syncthreads();
-  Acc<T> acc = product();
+  Acc<T> acc;
+  acc.zero();
+  mma_stage<T>(L, acc);
   __syncthreads();  // operands consumed
   acc_foreach<T>(acc, [&](int r, int c, double2 x) {
     if (n0 + c < c_hi) cv.p[(long)sp[f + r] * cv.ld + n0 + c] = x;
     L.br[r * T::PB + c] = x.x;  // X_f is the next product's right operand
     L.bi[r * T::PB + c] = x.y;
   });
-  // ---- Y = C_g - coupling X_f   (coupling: L21 below the first half, U12 right of the second)
-  stage_a([&](int r, int k) { return M[(long)sp[g + r] * a.ldm + r0 + f + k]; });
+  // ---- Y = C_g - acc_g - coupling X_f   (coupling: L21 below the first half, U12 right of the second)
+  stage_a(coupling(g, r0 + f));
   __syncthreads();
-  acc = product();
+  mma_stage<T>(L, acc_g);
   __syncthreads();
-  acc_foreach<T>(acc, [&](int r, int c, double2 x) {  // Y is the last product's right operand
-    const double2 cg = n0 + c < c_hi ? cv.p[(long)sp[g + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
-    L.br[r * T::PB + c] = cg.x - x.x;
-    L.bi[r * T::PB + c] = cg.y - x.y;
-  });
+  publish_diff(acc_g, g);
   // ---- X_g = inv_g Y
   stage_a([&](int r, int k) { return inv_g[r * H + k]; });
   __syncthreads();
-  acc = product();
+  acc.zero();
+  mma_stage<T>(L, acc);
   acc_foreach<T>(acc, [&](int r, int c, double2 x) {
     if (n0 + c < c_hi) cv.p[(long)sp[g + r] * cv.ld + n0 + c] = x;
   });
@@ -654,17 +678,34 @@ struct LuRun {
       hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream,
                          a, r0, rows, c_lo, c_hi);
   }
-  // a full 64-row block of two 32-column panels: one fused leaf (three matrix-core products)
+  // the fused 64-row leaf at rows r0 (p0 >= 0: with the update from the solved block at rows p0)
+  void leaf2x(bool upper, int r0, int p0, int c_lo, int c_hi) {
+    if (c_lo >= c_hi) return;
+    KernelScope ks_(ctx, "trsm");
+    const dim3 grid(cdiv(c_hi - c_lo, LuTileLeaf::BN), d.nmat);
+    if (upper)
+      hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi);
+    else
+      hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi);
+  }
+  bool fused_ok(int lo, int hi, int rows) const {
+    return W == 32 && a.inv != nullptr && hi - lo == rows && lo % 32 == 0;
+  }
+  // a full 64-row block of two 32-column panels: one fused leaf; a full 128-row block: two fused leaves,
+  // the second also applying the 64-deep update from the first
   bool leaf64(bool upper, int lo, int hi, int c_lo, int c_hi) {
-    if (W != 32 || a.inv == nullptr || hi - lo != 64 || lo % 32 != 0) return false;
-    if (c_lo < c_hi) {
-      KernelScope ks_(ctx, "trsm");
-      const dim3 grid(cdiv(c_hi - c_lo, LuTileLeaf::BN), d.nmat);
-      if (upper)
-        hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
-      else
-        hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, lo, c_lo, c_hi);
+    if (fused_ok(lo, hi, 128)) {
+      if (upper) {
+        leaf2x(true, lo + 64, -1, c_lo, c_hi);
+        leaf2x(true, lo, lo + 64, c_lo, c_hi);
+      } else {
+        leaf2x(false, lo, -1, c_lo, c_hi);
+        leaf2x(false, lo + 64, lo, c_lo, c_hi);
+      }
+      return true;
     }
+    if (!fused_ok(lo, hi, 64)) return false;
+    leaf2x(upper, lo, -1, c_lo, c_hi);
     return true;
   }
   // unit lower solve on rows [lo, hi) of columns [c_lo, c_hi)
