@@ -608,6 +608,8 @@ def main():
                          "calibrating the FETCH_SIZE and WRITE_SIZE counters)")
     ap.add_argument("--ceilings", action="store_true",
                     help="only measure this GPU's FP64/FP32 matrix-core, FP64 vector and copy rates")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the extra untimed passes that time the recursion (for profiler runs)")
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -656,10 +658,11 @@ def main():
     k_ms, k_launches, k_flops, k_bytes = timed_ctx.kernel_timer_read(with_flops=True)
     timed_ctx.kernel_timer(None)
     # one more (untimed) step with the recursion's kernels bracketed by HIP events: recursion TFLOP/s
-    rec_ms = []
-    pipe.run(recursion_ms=rec_ms)
-    torch.cuda.synchronize()
-    rec_alone_wall, rec_alone_kms = pipe.recursion_alone()
+    rec_ms, rec_alone_wall, rec_alone_kms = [], None, None
+    if not args.no_extra:
+        pipe.run(recursion_ms=rec_ms)
+        torch.cuda.synchronize()
+        rec_alone_wall, rec_alone_kms = pipe.recursion_alone()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
     mixed = args.mode == "mixed"
@@ -726,7 +729,7 @@ def main():
         "roofline": roof,
         # the recursion's algorithmic flops / the summed duration of its kernels (form, chain, LU) in one
         # step, measured with HIP events while the self-energies run beside it on the second stream
-        "recursion": dict(kernel_ms=round(sum(rec_ms), 2),
+        "recursion": None if args.no_extra else dict(kernel_ms=round(sum(rec_ms), 2),
                           tflops=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
                           frac_peak=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /
                                           (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4),
