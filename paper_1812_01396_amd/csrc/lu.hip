@@ -69,6 +69,12 @@ __device__ __forceinline__ bool skipped(const LuArgs &a, int mat) {
   return a.skip != nullptr && a.skip[mat >> a.skip_shift] != 0;
 }
 
+// Row `row` (logical order) of system mat's solution X, at right-hand-side column 0 (columns >= n of
+// the augmented matrix map to X's columns - n).
+__device__ __forceinline__ double2 *x_row(const LuArgs &a, int mat, int row) {
+  return a.X + (a.xoff ? a.xoff[mat] : (long)mat * a.sX) + (long)row * a.ldx - a.n;
+}
+
 static LuArgs make_args(const LuDesc &d) {
   LuArgs a;
   a.M = d.M; a.sM = d.sM; a.ldm = d.ldm; a.perm = d.perm; a.sP = d.sP;
@@ -483,7 +489,7 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int rows, i
 // Every workgroup reads all w rows of its columns before it writes them, so the update is in place.
 template <bool kUpper>
 __global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W, int r0, int rows,
-                                                                           int c_lo, int c_hi) {
+                                                                           int c_lo, int c_hi, int to_x) {
   using T = LuTileFlat;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sp[T::BM];
@@ -502,7 +508,10 @@ __global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs
   mma_loop<T>(la, lb, 0, w, n0, c_hi, 0, w, acc, lds);
   acc_foreach<T>(acc, [&](int r, int c, double2 val) {
     const int gc = n0 + c;
-    if (r < w && gc < c_hi) cv.p[(long)sp[r] * cv.ld + gc] = val;
+    if (r < w && gc < c_hi) {
+      cv.p[(long)sp[r] * cv.ld + gc] = val;
+      if (to_x) x_row(a, mat, r0 + r)[gc] = val;  // final rows of the upper solve: also the solution
+    }
   });
 }
 
@@ -519,7 +528,7 @@ using LuTileLeaf = TileCfg<32, 32, 32, 2, 2>;
 
 template <bool kUpper>
 __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int p0, int c_lo,
-                                                                             int c_hi) {
+                                                                             int c_hi, int to_x) {
   using T = LuTileLeaf;
   constexpr int H = 32;
   static_assert(T::BM == H && T::BN == H && T::BK == H && T::NT == 256, "leaf tile");
@@ -606,7 +615,10 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
   mma_stage<T>(L, acc);
   __syncthreads();  // operands consumed
   acc_foreach<T>(acc, [&](int r, int c, double2 x) {
-    if (n0 + c < c_hi) cv.p[(long)sp[f + r] * cv.ld + n0 + c] = x;
+    if (n0 + c < c_hi) {
+      cv.p[(long)sp[f + r] * cv.ld + n0 + c] = x;
+      if (to_x) x_row(a, mat, r0 + f + r)[n0 + c] = x;
+    }
     L.br[r * T::PB + c] = x.x;  // X_f is the next product's right operand
     L.bi[r * T::PB + c] = x.y;
   });
@@ -622,7 +634,10 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
   acc.zero();
   mma_stage<T>(L, acc);
   acc_foreach<T>(acc, [&](int r, int c, double2 x) {
-    if (n0 + c < c_hi) cv.p[(long)sp[g + r] * cv.ld + n0 + c] = x;
+    if (n0 + c < c_hi) {
+      cv.p[(long)sp[g + r] * cv.ld + n0 + c] = x;
+      if (to_x) x_row(a, mat, r0 + g + r)[n0 + c] = x;
+    }
   });
 }
 
@@ -667,13 +682,15 @@ struct LuRun {
   }
   // triangular-solve leaves cover up to TL rows
   static constexpr int TL = W;
+  // set during the upper right-hand-side solve when its leaves also write the solution X (no copy)
+  int to_x = 0;
   template <bool kUpper>
   void leaf(int r0, int rows, int c_lo, int c_hi) {
     if (c_lo >= c_hi) return;
     KernelScope ks_(ctx, "trsm");
     if (a.inv != nullptr)
       hipLaunchKernelGGL(k_lu_leaf<kUpper>, dim3(cdiv(c_hi - c_lo, LuTileFlat::BN), d.nmat), dim3(LuTileFlat::NT), 0,
-                         ctx->stream, a, W, r0, rows, c_lo, c_hi);
+                         ctx->stream, a, W, r0, rows, c_lo, c_hi, kUpper ? to_x : 0);
     else
       hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream,
                          a, r0, rows, c_lo, c_hi);
@@ -684,9 +701,10 @@ struct LuRun {
     KernelScope ks_(ctx, "trsm");
     const dim3 grid(cdiv(c_hi - c_lo, LuTileLeaf::BN), d.nmat);
     if (upper)
-      hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi);
+      hipLaunchKernelGGL(k_lu_leaf2x<true>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi,
+                         to_x);
     else
-      hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi);
+      hipLaunchKernelGGL(k_lu_leaf2x<false>, grid, dim3(LuTileLeaf::NT), 0, ctx->stream, a, r0, p0, c_lo, c_hi, 0);
   }
   bool fused_ok(int lo, int hi, int rows) const {
     return W == 32 && a.inv != nullptr && hi - lo == rows && lo % 32 == 0;
@@ -745,10 +763,16 @@ struct LuRun {
     if (do_factor) factor(0, d.n);
     if (d.nrhs > 0) {
       trsm_lower(0, d.n, d.n, d.n + d.nrhs);
+      // with matrix-core leaves every row of the upper solve is final when its leaf writes it: the
+      // leaves also write X, and no copy pass is needed
+      to_x = a.inv != nullptr ? 1 : 0;
       trsm_upper(0, d.n, d.n, d.n + d.nrhs);
-      const long total = (long)d.n * d.nrhs;
-      const int blocks = (int)std::min<long>((total + 255) / 256, 256);
-      hipLaunchKernelGGL(k_copy_out, dim3(blocks, d.nmat), dim3(256), 0, ctx->stream, a);
+      to_x = 0;
+      if (a.inv == nullptr) {
+        const long total = (long)d.n * d.nrhs;
+        const int blocks = (int)std::min<long>((total + 255) / 256, 256);
+        hipLaunchKernelGGL(k_copy_out, dim3(blocks, d.nmat), dim3(256), 0, ctx->stream, a);
+      }
     }
     return check_launch(ctx, "lu_solve");
   }
