@@ -531,7 +531,7 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
                                                                              int c_hi, int to_x) {
   using T = LuTileLeaf;
   constexpr int H = 32;
-  static_assert(T::BM == H && T::BN == H && T::BK == H && T::NT == 256, "leaf tile");
+  static_assert(T::BM == H && T::BK == H && H * H % T::NT == 0 && H * T::BN % T::NT == 0, "leaf tile");
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sp[2 * H], spp[2 * H];
   const int mat = blockIdx.y;
@@ -545,14 +545,15 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
     if (p0 >= 0) spp[tid] = perm[p0 + tid];
   }
   __syncthreads();
-  const int n0 = c_lo + blockIdx.x * H;
+  const int n0 = c_lo + blockIdx.x * T::BN;
   const double2 *inv = a.inv + (long)mat * a.sInv;
   const int kind = kUpper ? 1 : 0;
   const int f = kUpper ? H : 0, g = kUpper ? 0 : H;  // the half solved first, and the other
   const double2 *inv_f = inv + ((long)(r0 + f) / H * 2 + kind) * H * H;
   const double2 *inv_g = inv + ((long)(r0 + g) / H * 2 + kind) * H * H;
   Lds<T> L(lds);
-  constexpr int E = H * H / T::NT;  // elements per thread of a 32 x 32 operand
+  constexpr int E = H * H / T::NT;         // elements per thread of a 32 x 32 operand
+  constexpr int EB = H * T::BN / T::NT;   // elements per thread of 32 right-hand-side rows
   // A operand (r, k) -> planes [k][r];  B operand (k, c) -> planes [k][c]
   auto stage_a = [&](auto load) {
     double2 v[E];
@@ -565,16 +566,16 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
       L.ai[k * T::PA + r] = v[e].y;
     }
   };
-  auto stage_b_rows = [&](const int *rowmap) {  // 32 right-hand-side rows (columns n0..n0+31)
-    double2 v[E];
+  auto stage_b_rows = [&](const int *rowmap) {  // 32 right-hand-side rows (columns n0 .. n0 + BN - 1)
+    double2 v[EB];
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
+    for (int e = 0; e < EB; ++e) {
+      const int k = (tid + e * T::NT) / T::BN, c = (tid + e * T::NT) % T::BN;
       v[e] = n0 + c < c_hi ? cv.p[(long)rowmap[k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) {
-      const int k = (tid + e * T::NT) / H, c = (tid + e * T::NT) % H;
+    for (int e = 0; e < EB; ++e) {
+      const int k = (tid + e * T::NT) / T::BN, c = (tid + e * T::NT) % T::BN;
       L.br[k * T::PB + c] = v[e].x;
       L.bi[k * T::PB + c] = v[e].y;
     }
