@@ -368,6 +368,251 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   }
 }
 
+// ------------------------------------------------------------------ two-level 32-column panel
+
+// Columns [c0 + j0, c0 + j0 + wh) of a panel whose rows (one logical row lr = threadIdx.x per thread) hold
+// these H columns in v: pivot search over logical rows >= j0 + j, interchange (registers and row map),
+// multipliers and rank-1 updates, with the same rotation scheme as k_panel.  Sets bit j of dead when
+// column j has no nonzero pivot (its rows then stay unscaled and no update is applied).
+template <int H>
+__device__ __forceinline__ void panel_half(double2 (&v)[H], int nrows, int j0, int wh, int c0, int *sperm,
+                                           double *red_v, int *red_i, double2 (*rowbuf)[H], int &zero_col,
+                                           unsigned &dead) {
+  const int lr = threadIdx.x, lane = lr & 63, wave = lr >> 6, nw = blockDim.x >> 6;
+#pragma unroll 1
+  for (int j = 0; j < wh; ++j) {
+    const int p = j0 + j;  // logical row (and panel column) of this pivot
+    double bv = -1.0;
+    int bi = INT_MAX;
+    if (lr >= p && lr < nrows) {
+      bv = cabs1(v[0]);
+      bi = lr;
+    }
+    auto merge = [&](double ov, int oi) {
+      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+    };
+    merge(dpp_double<0xB1>(bv), dpp_int<0xB1>(bi));
+    merge(dpp_double<0x4E>(bv), dpp_int<0x4E>(bi));
+    merge(dpp_double<0x141>(bv), dpp_int<0x141>(bi));
+    merge(dpp_double<0x140>(bv), dpp_int<0x140>(bi));
+    merge(__shfl_xor(bv, 16), __shfl_xor(bi, 16));
+    merge(__shfl_xor(bv, 32), __shfl_xor(bi, 32));
+    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+    __syncthreads();
+    bv = red_v[0];
+    bi = red_i[0];
+    for (int ww = 1; ww < nw; ++ww) merge(red_v[ww], red_i[ww]);
+    const int piv = (bi >= p && bi < nrows) ? bi : p;
+    if (lr == piv) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) st2(rowbuf[0][c], v[c]);
+    }
+    if (lr == p && piv != p) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) st2(rowbuf[1][c], v[c]);
+    }
+    __syncthreads();
+    if (lr == p) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[0][c]);
+    } else if (lr == piv) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[1][c]);
+    }
+    if (lr == 0 && piv != p) {
+      const int t = sperm[p];
+      sperm[p] = sperm[piv];
+      sperm[piv] = t;
+    }
+    const double2 u = ld2(rowbuf[0][0]);
+    const bool live = !(u.x == 0.0 && u.y == 0.0);
+    if (!live) {
+      dead |= 1u << j;
+      if (zero_col == 0) zero_col = c0 + p + 1;
+    }
+    const double2 ui = live ? crecip(u) : make_double2(0.0, 0.0);
+    const bool below = live && lr > p && lr < nrows;
+    const double2 v0 = v[0];
+    const double2 pm = cmul(v0, ui);
+    const double lx = below ? pm.x : v0.x, ly = below ? pm.y : v0.y;
+    const double mx = below ? pm.x : 0.0, my = below ? pm.y : 0.0;
+    const int live_pos = H - 1 - j;
+#pragma unroll
+    for (int g = 0; g < (H - 1 + 3) / 4; ++g) {
+      if (4 * g + 4 <= live_pos) {
+#pragma unroll
+        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) {
+          const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
+          const double vx = v[c + 1].x, vy = v[c + 1].y;
+          v[c].x = vx - mx * ux + my * uy;
+          v[c].y = vy - mx * uy - my * ux;
+        }
+      } else if (4 * g >= live_pos) {
+#pragma unroll
+        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) v[c] = v[c + 1];
+      } else {
+#pragma unroll
+        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) {
+          const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
+          const double vx = v[c + 1].x, vy = v[c + 1].y;
+          const bool upd = c < live_pos;
+          v[c].x = upd ? vx - mx * ux + my * uy : vx;
+          v[c].y = upd ? vy - mx * uy - my * ux : vy;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    v[H - 1].x = lx;
+    v[H - 1].y = ly;
+  }
+#pragma unroll 1
+  for (int t = wh; t < H; ++t) {  // a narrow half: finish the rotation
+    const double2 x0 = v[0];
+#pragma unroll
+    for (int c = 0; c < H - 1; ++c) v[c] = v[c + 1];
+    v[H - 1] = x0;
+  }
+}
+
+// The 32-column panel in two halves of 16 (n <= 512, one logical row per thread): factor the left half,
+// write it back, load the right half, apply the left half's rank-1 updates to it in column order, factor
+// it.  Every element sees the same operations in the same order as in the one-pass panel (so the same
+// pivots), while at most 2 x 16 complex entries per row are live: the kernel fits three waves' register
+// budget and can share a CU with other work, where a whole 32-column row per thread needs the whole
+// register file.  Also leaves the inverses of the diagonal block's triangles, as k_panel.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_panel32(LuArgs a, int c0) {
+  constexpr int W = 32, H = 16, CP = 64 + 1;
+  const int mat = blockIdx.x;
+  if (skipped(a, mat)) return;
+  const int lr = threadIdx.x;
+  double2 *M = a.M + (long)mat * a.sM;
+  int *perm = a.perm + (long)mat * a.sP;
+  const int nrows = a.n - c0;
+  const int w = min(W, nrows), wl = min(H, w), wr = w - wl;
+  const long ld = a.ldm;
+
+  __shared__ int sperm[512];
+  __shared__ double2 tri_l[W][W + 1], tri_u[W][W + 1];
+  __shared__ double2 rdiag[W];
+  __shared__ double eye_r[W * CP], eye_i[W * CP];
+  __shared__ double red_v[8];
+  __shared__ int red_i[8];
+  __shared__ double2 rowbuf[2][H];
+
+  if (lr < nrows) sperm[lr] = perm[c0 + lr];
+  __syncthreads();
+  const bool inv = a.inv != nullptr;
+  if (inv) {
+    for (int idx = lr; idx < W * (W + 1); idx += blockDim.x) {
+      (&tri_l[0][0])[idx] = make_double2(0.0, 0.0);
+      (&tri_u[0][0])[idx] = make_double2(0.0, 0.0);
+    }
+    for (int idx = lr; idx < W * CP; idx += blockDim.x) {
+      const int i = idx / CP, c = idx % CP;
+      eye_r[idx] = (i == c && i < w) ? 1.0 : 0.0;
+      eye_i[idx] = 0.0;
+    }
+    if (lr < W) rdiag[lr] = make_double2(0.0, 0.0);
+  }
+  int zero_col = 0;
+  unsigned dead = 0;
+  // v: the half being factored (one code path for both halves keeps one register assignment)
+  double2 v[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) v[c] = (lr < nrows && c < wl) ? M[(long)sperm[lr] * ld + c0 + c] : make_double2(0.0, 0.0);
+#pragma unroll 1
+  for (int half = 0; half < 2; ++half) {
+    const int j0 = half * H, wh = half ? wr : wl;
+    if (half == 1) {
+      if (wr == 0) break;  // uniform
+      // ---- the left half's updates on the right half, column by column (v holds the factored left half:
+      // multipliers below each pivot, U above)
+      double2 r[H];
+#pragma unroll
+      for (int c = 0; c < H; ++c)
+        r[c] = (lr < nrows && c < wr) ? M[(long)sperm[lr] * ld + c0 + H + c] : make_double2(0.0, 0.0);
+#pragma unroll
+      for (int k = 0; k < H; ++k) {
+        if (k < wl) {  // uniform, as is kl; one barrier per column keeps the two row buffers alternating
+          const bool kl = !((dead >> k) & 1u);
+          if (kl && lr == k) {
+#pragma unroll
+            for (int c = 0; c < H; ++c) st2(rowbuf[k & 1][c], r[c]);
+          }
+          __syncthreads();
+          if (kl && lr > k && lr < nrows) {
+            const double mx = v[k].x, my = v[k].y;
+#pragma unroll
+            for (int g = 0; g < H / 4; ++g) {
+#pragma unroll
+              for (int c = 4 * g; c < 4 * g + 4; ++c) {
+                const double ux = rowbuf[k & 1][c].x, uy = rowbuf[k & 1][c].y;
+                const double vx = r[c].x, vy = r[c].y;
+                r[c].x = vx - mx * ux + my * uy;
+                r[c].y = vy - mx * uy - my * ux;
+              }
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < H; ++c) v[c] = r[c];
+      __syncthreads();  // row-buffer reads done before the right half's pivots reuse them
+      if (inv && lr < wl) {  // U12 rows are final
+#pragma unroll
+        for (int c = 0; c < H; ++c)
+          if (c < wr) st2(tri_u[lr][H + c], v[c]);
+      }
+    }
+    unsigned dh = 0;
+    panel_half<H>(v, nrows, j0, wh, c0, sperm, red_v, red_i, rowbuf, zero_col, dh);
+    if (half == 0) dead = dh;
+    __syncthreads();  // row map after this half
+    if (lr < nrows) {
+#pragma unroll
+      for (int c = 0; c < H; ++c)
+        if (c < wh) M[(long)sperm[lr] * ld + c0 + j0 + c] = v[c];
+    }
+    // this half's part of the diagonal block: rows j0 .. j0 + wh - 1 are final now
+    if (inv && lr >= j0 && lr < j0 + wh) {
+      const int i = lr - j0;
+#pragma unroll
+      for (int c = 0; c < H; ++c) {
+        if (c < i) st2(tri_l[lr][j0 + c], v[c]);
+        if (c > i && c < wh) st2(tri_u[lr][j0 + c], v[c]);
+        if (c == i) st2(rdiag[lr], crecip(v[c]));
+      }
+    }
+  }
+  if (inv && wr > 0) {
+    // the left half's rows below the first 16 pivots were moved by the right half's interchanges: their
+    // part of the diagonal block is read back from memory
+    __syncthreads();
+    if (lr >= H && lr < w) {
+#pragma unroll
+      for (int c = 0; c < H; ++c) st2(tri_l[lr][c], M[(long)sperm[lr] * ld + c0 + c]);
+    }
+  }
+  if (lr < nrows) perm[c0 + lr] = sperm[lr];
+  if (lr == 0) {
+    if (c0 == 0) a.zp[mat] = zero_col;
+    else if (zero_col != 0 && a.zp[mat] == 0) a.zp[mat] = zero_col;
+  }
+  if (inv) {
+    __syncthreads();
+    double2 *dst = a.inv + (long)mat * a.sInv + (long)(c0 / W) * 2 * W * W;
+    if (lr < 256) {
+      tile_trsm<W, CP, false>(eye_r, eye_i, tri_l, rdiag, w, [&](int i, int col, double2 x) {
+        if (col < w) dst[i * W + col] = x;
+      });
+      tile_trsm<W, CP, true>(eye_r, eye_i, tri_u, rdiag, w, [&](int i, int col, double2 x) {
+        if (col < w) dst[W * W + i * W + col] = x;
+      });
+    }
+  }
+}
+
 // ------------------------------------------------------------------ products and triangular leaves
 
 using LuTile = TileCfg<64, 64, 16, 2, 2>;
@@ -751,7 +996,10 @@ struct LuRun {
       // at least four waves: they invert the panel's diagonal block at the end
       const int threads = std::min(LB, std::max(256, cdiv(rows, 64) * 64));
       KernelScope ks_(ctx, "panel");
-      hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+      if constexpr (W == 32 && R == 1 && LB == 512)
+        hipLaunchKernelGGL(k_panel32, dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+      else
+        hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
       return;
     }
     const int cm = mid(c0, c1);
