@@ -95,14 +95,14 @@ __global__ void k_identity_perm(int *perm, long sP, int n) {
 // In-tile triangular solve T x = c for the 64 columns of a staged tile, by substitution (LAPACK's
 // triangular-solve arithmetic).  Each wave owns 16 columns; 4 lanes share a column and each keeps the
 // rows j = part (mod 4), so a row step is a 4-lane partial dot product and two cross-lane additions.
-//   cr, ci: staged tile planes [row][kCP];  tri: W x W triangle [i][j] (pitch W + 1) holding only the
+//   rhs(i, col): element (i, col) of c (a staged tile, or generated);  tri: W x W triangle [i][j] (pitch W + 1) holding only the
 //   strictly lower (!kUpper) or strictly upper (kUpper) entries, zero elsewhere;  rdiag: reciprocals of
 //   the diagonal (kUpper);  kUpper: false = unit lower (forward), true = upper (backward); w <= W rows.
 // Unsolved rows hold zero in x and the triangle is zero outside its part, so every row step reads the
 // whole row of the triangle unconditionally.  out(i, col, x) receives every solved element (i < w).
-template <int W, int kCP, bool kUpper, class Out>
-__device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, const double2 (*tri)[W + 1],
-                                          const double2 *rdiag, int w, Out &&out) {
+template <int W, bool kUpper, class Rhs, class Out>
+__device__ __forceinline__ void tile_trsm(Rhs &&rhs, const double2 (*tri)[W + 1], const double2 *rdiag, int w,
+                                          Out &&out) {
   constexpr int NX = (W + 3) / 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col = wave * 16 + (lane >> 2), part = lane & 3;
@@ -125,7 +125,8 @@ __device__ __forceinline__ void tile_trsm(const double *cr, const double *ci, co
     ax += dpp_double<0x4E>(ax);
     ay += dpp_double<0x4E>(ay);
     if (part == (i & 3)) {
-      double2 v = make_double2(cr[i * kCP + col] - ax, ci[i * kCP + col] - ay);
+      const double2 ci = rhs(i, col);
+      double2 v = make_double2(ci.x - ax, ci.y - ay);
       if (kUpper) v = cmul(v, ld2(rdiag[i]));
       const int ti = i >> 2;
 #pragma unroll
@@ -161,12 +162,10 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   const long ld = a.ldm;
 
   __shared__ int sperm[LB * R];
-  // inversion of the diagonal block: its strict lower and strict upper triangles, the reciprocals of
-  // its diagonal and identity right-hand sides as real and imaginary planes
-  constexpr int CP = 64 + 1;
+  // inversion of the diagonal block: its strict lower and strict upper triangles and the reciprocals of
+  // its diagonal (the identity right-hand sides are generated)
   __shared__ double2 tri_l[W][W + 1], tri_u[W][W + 1];
   __shared__ double2 rdiag[W];
-  __shared__ double eye_r[W * CP], eye_i[W * CP];
   __shared__ double red_v[16];
   __shared__ int red_i[16];
   __shared__ double2 rowbuf[2][W];
@@ -332,11 +331,6 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
         }
       }
     }
-    for (int idx = tid; idx < W * CP; idx += T) {
-      const int i = idx / CP, c = idx % CP;
-      eye_r[idx] = (i == c && i < w) ? 1.0 : 0.0;
-      eye_i[idx] = 0.0;
-    }
   }
 
   // ---- write the factored panel back (rows stay in their physical place) and the row map
@@ -357,256 +351,214 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
   if (a.inv != nullptr) {  // (after the write-back, so the panel's registers are free)
     __syncthreads();
     double2 *dst = a.inv + (long)mat * a.sInv + (long)(c0 / W) * 2 * W * W;
+    auto eye = [&](int i, int col) { return make_double2(i == col && i < w ? 1.0 : 0.0, 0.0); };
     if (tid < 256) {
-      tile_trsm<W, CP, false>(eye_r, eye_i, tri_l, rdiag, w, [&](int i, int col, double2 x) {
+      tile_trsm<W, false>(eye, tri_l, rdiag, w, [&](int i, int col, double2 x) {
         if (col < w) dst[i * W + col] = x;
       });
-      tile_trsm<W, CP, true>(eye_r, eye_i, tri_u, rdiag, w, [&](int i, int col, double2 x) {
+      tile_trsm<W, true>(eye, tri_u, rdiag, w, [&](int i, int col, double2 x) {
         if (col < w) dst[W * W + i * W + col] = x;
       });
     }
   }
 }
 
-// ------------------------------------------------------------------ two-level 32-column panel
+// ------------------------------------------------------------------ 32-column panel in quarters
 
-// Columns [c0 + j0, c0 + j0 + wh) of a panel whose rows (one logical row lr = threadIdx.x per thread) hold
-// these H columns in v: pivot search over logical rows >= j0 + j, interchange (registers and row map),
-// multipliers and rank-1 updates, with the same rotation scheme as k_panel.  Sets bit j of dead when
-// column j has no nonzero pivot (its rows then stay unscaled and no update is applied).
-template <int H>
-__device__ __forceinline__ void panel_half(double2 (&v)[H], int nrows, int j0, int wh, int c0, int *sperm,
-                                           double *red_v, int *red_i, double2 (*rowbuf)[H], int &zero_col,
-                                           unsigned &dead) {
-  const int lr = threadIdx.x, lane = lr & 63, wave = lr >> 6, nw = blockDim.x >> 6;
-#pragma unroll 1
-  for (int j = 0; j < wh; ++j) {
-    const int p = j0 + j;  // logical row (and panel column) of this pivot
-    double bv = -1.0;
-    int bi = INT_MAX;
-    if (lr >= p && lr < nrows) {
-      bv = cabs1(v[0]);
-      bi = lr;
-    }
-    auto merge = [&](double ov, int oi) {
-      if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-    };
-    merge(dpp_double<0xB1>(bv), dpp_int<0xB1>(bi));
-    merge(dpp_double<0x4E>(bv), dpp_int<0x4E>(bi));
-    merge(dpp_double<0x141>(bv), dpp_int<0x141>(bi));
-    merge(dpp_double<0x140>(bv), dpp_int<0x140>(bi));
-    merge(__shfl_xor(bv, 16), __shfl_xor(bi, 16));
-    merge(__shfl_xor(bv, 32), __shfl_xor(bi, 32));
-    if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
-    __syncthreads();
-    bv = red_v[0];
-    bi = red_i[0];
-    for (int ww = 1; ww < nw; ++ww) merge(red_v[ww], red_i[ww]);
-    const int piv = (bi >= p && bi < nrows) ? bi : p;
-    if (lr == piv) {
-#pragma unroll
-      for (int c = 0; c < H; ++c) st2(rowbuf[0][c], v[c]);
-    }
-    if (lr == p && piv != p) {
-#pragma unroll
-      for (int c = 0; c < H; ++c) st2(rowbuf[1][c], v[c]);
-    }
-    __syncthreads();
-    if (lr == p) {
-#pragma unroll
-      for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[0][c]);
-    } else if (lr == piv) {
-#pragma unroll
-      for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[1][c]);
-    }
-    if (lr == 0 && piv != p) {
-      const int t = sperm[p];
-      sperm[p] = sperm[piv];
-      sperm[piv] = t;
-    }
-    const double2 u = ld2(rowbuf[0][0]);
-    const bool live = !(u.x == 0.0 && u.y == 0.0);
-    if (!live) {
-      dead |= 1u << j;
-      if (zero_col == 0) zero_col = c0 + p + 1;
-    }
-    const double2 ui = live ? crecip(u) : make_double2(0.0, 0.0);
-    const bool below = live && lr > p && lr < nrows;
-    const double2 v0 = v[0];
-    const double2 pm = cmul(v0, ui);
-    const double lx = below ? pm.x : v0.x, ly = below ? pm.y : v0.y;
-    const double mx = below ? pm.x : 0.0, my = below ? pm.y : 0.0;
-    const int live_pos = H - 1 - j;
-#pragma unroll
-    for (int g = 0; g < (H - 1 + 3) / 4; ++g) {
-      if (4 * g + 4 <= live_pos) {
-#pragma unroll
-        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) {
-          const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
-          const double vx = v[c + 1].x, vy = v[c + 1].y;
-          v[c].x = vx - mx * ux + my * uy;
-          v[c].y = vy - mx * uy - my * ux;
-        }
-      } else if (4 * g >= live_pos) {
-#pragma unroll
-        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) v[c] = v[c + 1];
-      } else {
-#pragma unroll
-        for (int c = 4 * g; c < 4 * g + 4 && c < H - 1; ++c) {
-          const double ux = rowbuf[0][c + 1].x, uy = rowbuf[0][c + 1].y;
-          const double vx = v[c + 1].x, vy = v[c + 1].y;
-          const bool upd = c < live_pos;
-          v[c].x = upd ? vx - mx * ux + my * uy : vx;
-          v[c].y = upd ? vy - mx * uy - my * ux : vy;
-        }
-      }
-      __builtin_amdgcn_sched_barrier(0);
-    }
-    v[H - 1].x = lx;
-    v[H - 1].y = ly;
-  }
-#pragma unroll 1
-  for (int t = wh; t < H; ++t) {  // a narrow half: finish the rotation
-    const double2 x0 = v[0];
-#pragma unroll
-    for (int c = 0; c < H - 1; ++c) v[c] = v[c + 1];
-    v[H - 1] = x0;
-  }
-}
-
-// The 32-column panel in two halves of 16 (n <= 512, one logical row per thread): factor the left half,
-// write it back, load the right half, apply the left half's rank-1 updates to it in column order, factor
-// it.  Every element sees the same operations in the same order as in the one-pass panel (so the same
-// pivots), while at most 2 x 16 complex entries per row are live: the kernel fits three waves' register
-// budget and can share a CU with other work, where a whole 32-column row per thread needs the whole
-// register file.  Also leaves the inverses of the diagonal block's triangles, as k_panel.
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) k_panel32(LuArgs a, int c0) {
-  constexpr int W = 32, H = 16, CP = 64 + 1;
+// The 32-column panel (n <= 512, one logical row per thread) in four quarters of 8 columns.  Quarter q is
+// loaded, receives the updates of the 8q columns before it (first the rows of their pivots, in pivot
+// order, then every row below them as one product with those rows), and is factored with its columns
+// unrolled, then written back.  Every element receives the updates of a one-pass panel in the same
+// column order (the compiled rounding may differ in the last bit), while a thread holds 8 complex entries
+// of its row instead of 32: the workgroup needs about a quarter of a CU's register file and shares the CU
+// with other work, where a whole row per thread needs all of it.  Also leaves the inverses of the
+// diagonal block's triangles.
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_panel32(LuArgs a, int c0) {
+  constexpr int W = 32, H = 8, NQ = W / H;
   const int mat = blockIdx.x;
   if (skipped(a, mat)) return;
-  const int lr = threadIdx.x;
+  const int lr = threadIdx.x, lane = lr & 63, wave = lr >> 6, nw = blockDim.x >> 6;
   double2 *M = a.M + (long)mat * a.sM;
   int *perm = a.perm + (long)mat * a.sP;
   const int nrows = a.n - c0;
-  const int w = min(W, nrows), wl = min(H, w), wr = w - wl;
+  const int w = min(W, nrows);
   const long ld = a.ldm;
 
   __shared__ int sperm[512];
   __shared__ double2 tri_l[W][W + 1], tri_u[W][W + 1];
   __shared__ double2 rdiag[W];
-  __shared__ double eye_r[W * CP], eye_i[W * CP];
   __shared__ double red_v[8];
   __shared__ int red_i[8];
   __shared__ double2 rowbuf[2][H];
+  __shared__ double2 ub[W - H][H];          // the quarter's part of the earlier pivot rows (final)
+  __shared__ double2 lt[W - H][W - H + 1];  // multipliers among the earlier pivot rows
 
   if (lr < nrows) sperm[lr] = perm[c0 + lr];
   __syncthreads();
-  const bool inv = a.inv != nullptr;
-  if (inv) {
-    for (int idx = lr; idx < W * (W + 1); idx += blockDim.x) {
-      (&tri_l[0][0])[idx] = make_double2(0.0, 0.0);
-      (&tri_u[0][0])[idx] = make_double2(0.0, 0.0);
-    }
-    for (int idx = lr; idx < W * CP; idx += blockDim.x) {
-      const int i = idx / CP, c = idx % CP;
-      eye_r[idx] = (i == c && i < w) ? 1.0 : 0.0;
-      eye_i[idx] = 0.0;
-    }
-    if (lr < W) rdiag[lr] = make_double2(0.0, 0.0);
-  }
   int zero_col = 0;
-  unsigned dead = 0;
-  // v: the half being factored (one code path for both halves keeps one register assignment)
-  double2 v[H];
-#pragma unroll
-  for (int c = 0; c < H; ++c) v[c] = (lr < nrows && c < wl) ? M[(long)sperm[lr] * ld + c0 + c] : make_double2(0.0, 0.0);
+  unsigned dead = 0;  // bit k: column k had no nonzero pivot (no update from it)
 #pragma unroll 1
-  for (int half = 0; half < 2; ++half) {
-    const int j0 = half * H, wh = half ? wr : wl;
-    if (half == 1) {
-      if (wr == 0) break;  // uniform
-      // ---- the left half's updates on the right half, column by column (v holds the factored left half:
-      // multipliers below each pivot, U above)
-      double2 r[H];
+  for (int q = 0; q < NQ; ++q) {
+    const int j0 = q * H, wh = min(H, w - j0);
+    if (wh <= 0) break;  // uniform
+    double2 v[H];
 #pragma unroll
-      for (int c = 0; c < H; ++c)
-        r[c] = (lr < nrows && c < wr) ? M[(long)sperm[lr] * ld + c0 + H + c] : make_double2(0.0, 0.0);
+    for (int c = 0; c < H; ++c)
+      v[c] = (lr < nrows && c < wh) ? M[(long)sperm[lr] * ld + c0 + j0 + c] : make_double2(0.0, 0.0);
+    if (q > 0) {
+      // ---- the earlier columns' updates.  Their multipliers among the first j0 rows, into LDS:
+      for (int idx = lr; idx < j0 * j0; idx += blockDim.x) {
+        const int i = idx / j0, k = idx % j0;
+        if (k < i) lt[i][k] = M[(long)sperm[i] * ld + c0 + k];
+      }
+      __syncthreads();
+      // the pivot rows themselves, in pivot order (row k is final once the columns before k are applied)
+#pragma unroll 1
+      for (int k = 0; k < j0; ++k) {
+        const bool kl = !((dead >> k) & 1u);  // uniform
+        if (lr == k) {
 #pragma unroll
-      for (int k = 0; k < H; ++k) {
-        if (k < wl) {  // uniform, as is kl; one barrier per column keeps the two row buffers alternating
-          const bool kl = !((dead >> k) & 1u);
-          if (kl && lr == k) {
+          for (int c = 0; c < H; ++c) st2(ub[k][c], v[c]);
+        }
+        __syncthreads();
+        if (kl && lr > k && lr < j0) {
+          const double mx = lt[lr][k].x, my = lt[lr][k].y;
 #pragma unroll
-            for (int c = 0; c < H; ++c) st2(rowbuf[k & 1][c], r[c]);
+          for (int c = 0; c < H; ++c) {
+            const double ux = ub[k][c].x, uy = ub[k][c].y;
+            const double vx = v[c].x, vy = v[c].y;
+            v[c].x = vx - mx * ux + my * uy;
+            v[c].y = vy - mx * uy - my * ux;
           }
-          __syncthreads();
-          if (kl && lr > k && lr < nrows) {
-            const double mx = v[k].x, my = v[k].y;
+        }
+      }
+      // every row below them: v -= L[lr, 0:j0] U[0:j0, quarter], the columns in order
+      if (lr >= j0 && lr < nrows) {
+        const double2 *lrow = M + (long)sperm[lr] * ld + c0;
+#pragma unroll 1
+        for (int kc = 0; kc < j0; kc += 4) {
+          double2 lk[4];
 #pragma unroll
-            for (int g = 0; g < H / 4; ++g) {
+          for (int e = 0; e < 4; ++e) lk[e] = lrow[kc + e];
 #pragma unroll
-              for (int c = 4 * g; c < 4 * g + 4; ++c) {
-                const double ux = rowbuf[k & 1][c].x, uy = rowbuf[k & 1][c].y;
-                const double vx = r[c].x, vy = r[c].y;
-                r[c].x = vx - mx * ux + my * uy;
-                r[c].y = vy - mx * uy - my * ux;
+          for (int e = 0; e < 4; ++e) {
+            const int k = kc + e;
+            if (!((dead >> k) & 1u)) {  // uniform
+              const double mx = lk[e].x, my = lk[e].y;
+#pragma unroll
+              for (int c = 0; c < H; ++c) {
+                const double ux = ub[k][c].x, uy = ub[k][c].y;
+                const double vx = v[c].x, vy = v[c].y;
+                v[c].x = vx - mx * ux + my * uy;
+                v[c].y = vy - mx * uy - my * ux;
               }
-              __builtin_amdgcn_sched_barrier(0);
             }
           }
         }
       }
+    }
+    // ---- factor the quarter's columns
 #pragma unroll
-      for (int c = 0; c < H; ++c) v[c] = r[c];
-      __syncthreads();  // row-buffer reads done before the right half's pivots reuse them
-      if (inv && lr < wl) {  // U12 rows are final
+    for (int j = 0; j < H; ++j) {
+      if (j < wh) {  // uniform
+        const int p = j0 + j;  // logical row (and panel column) of this pivot
+        double bv = -1.0;
+        int bi = INT_MAX;
+        if (lr >= p && lr < nrows) {
+          bv = cabs1(v[j]);
+          bi = lr;
+        }
+        auto merge = [&](double ov, int oi) {
+          if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
+        };
+        merge(dpp_double<0xB1>(bv), dpp_int<0xB1>(bi));
+        merge(dpp_double<0x4E>(bv), dpp_int<0x4E>(bi));
+        merge(dpp_double<0x141>(bv), dpp_int<0x141>(bi));
+        merge(dpp_double<0x140>(bv), dpp_int<0x140>(bi));
+        merge(__shfl_xor(bv, 16), __shfl_xor(bi, 16));
+        merge(__shfl_xor(bv, 32), __shfl_xor(bi, 32));
+        if (lane == 0) { red_v[wave] = bv; red_i[wave] = bi; }
+        __syncthreads();
+        bv = red_v[0];
+        bi = red_i[0];
+        for (int ww = 1; ww < nw; ++ww) merge(red_v[ww], red_i[ww]);
+        const int piv = (bi >= p && bi < nrows) ? bi : p;  // no finite candidate: keep the diagonal row
+        // interchange logical rows p and piv (the quarter's entries travel; earlier quarters' entries stay
+        // in their physical rows, which the row map follows)
+        if (lr == piv) {
 #pragma unroll
-        for (int c = 0; c < H; ++c)
-          if (c < wr) st2(tri_u[lr][H + c], v[c]);
+          for (int c = 0; c < H; ++c) st2(rowbuf[0][c], v[c]);
+        }
+        if (lr == p && piv != p) {
+#pragma unroll
+          for (int c = 0; c < H; ++c) st2(rowbuf[1][c], v[c]);
+        }
+        __syncthreads();
+        if (lr == p) {
+#pragma unroll
+          for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[0][c]);
+        } else if (lr == piv) {
+#pragma unroll
+          for (int c = 0; c < H; ++c) v[c] = ld2(rowbuf[1][c]);
+        }
+        if (lr == 0 && piv != p) {
+          const int t = sperm[p];
+          sperm[p] = sperm[piv];
+          sperm[piv] = t;
+        }
+        const double2 u = ld2(rowbuf[0][j]);
+        const bool live = !(u.x == 0.0 && u.y == 0.0);
+        if (!live) {
+          dead |= 1u << p;
+          if (zero_col == 0) zero_col = c0 + p + 1;
+        }
+        if (live && lr > p && lr < nrows) {
+          const double2 m = cmul(v[j], crecip(u));
+          v[j] = m;
+#pragma unroll
+          for (int c = j + 1; c < H; ++c) {
+            const double ux = rowbuf[0][c].x, uy = rowbuf[0][c].y;
+            const double vx = v[c].x, vy = v[c].y;
+            v[c].x = vx - m.x * ux + m.y * uy;
+            v[c].y = vy - m.x * uy - m.y * ux;
+          }
+        }
       }
     }
-    unsigned dh = 0;
-    panel_half<H>(v, nrows, j0, wh, c0, sperm, red_v, red_i, rowbuf, zero_col, dh);
-    if (half == 0) dead = dh;
-    __syncthreads();  // row map after this half
+    __syncthreads();  // row map after this quarter
     if (lr < nrows) {
 #pragma unroll
       for (int c = 0; c < H; ++c)
         if (c < wh) M[(long)sperm[lr] * ld + c0 + j0 + c] = v[c];
     }
-    // this half's part of the diagonal block: rows j0 .. j0 + wh - 1 are final now
-    if (inv && lr >= j0 && lr < j0 + wh) {
-      const int i = lr - j0;
-#pragma unroll
-      for (int c = 0; c < H; ++c) {
-        if (c < i) st2(tri_l[lr][j0 + c], v[c]);
-        if (c > i && c < wh) st2(tri_u[lr][j0 + c], v[c]);
-        if (c == i) st2(rdiag[lr], crecip(v[c]));
-      }
-    }
-  }
-  if (inv && wr > 0) {
-    // the left half's rows below the first 16 pivots were moved by the right half's interchanges: their
-    // part of the diagonal block is read back from memory
-    __syncthreads();
-    if (lr >= H && lr < w) {
-#pragma unroll
-      for (int c = 0; c < H; ++c) st2(tri_l[lr][c], M[(long)sperm[lr] * ld + c0 + c]);
-    }
+    __syncthreads();  // the next quarter reads these multipliers (other threads' rows)
   }
   if (lr < nrows) perm[c0 + lr] = sperm[lr];
   if (lr == 0) {
     if (c0 == 0) a.zp[mat] = zero_col;
     else if (zero_col != 0 && a.zp[mat] == 0) a.zp[mat] = zero_col;
   }
-  if (inv) {
+  if (a.inv != nullptr) {
+    // ---- inverses of the diagonal block's unit-lower and upper triangles (as in k_panel), the block read
+    // back from its final rows
+    if (lr < W) {
+#pragma unroll 4
+      for (int c = 0; c < W; ++c) {
+        const bool in = lr < w && c < w;
+        const double2 x = in ? M[(long)sperm[lr] * ld + c0 + c] : make_double2(0.0, 0.0);
+        st2(tri_l[lr][c], c < lr ? x : make_double2(0.0, 0.0));
+        st2(tri_u[lr][c], c > lr ? x : make_double2(0.0, 0.0));
+        if (c == lr) st2(rdiag[lr], in ? crecip(x) : make_double2(0.0, 0.0));
+      }
+    }
     __syncthreads();
     double2 *dst = a.inv + (long)mat * a.sInv + (long)(c0 / W) * 2 * W * W;
+    auto eye = [&](int i, int col) { return make_double2(i == col && i < w ? 1.0 : 0.0, 0.0); };
     if (lr < 256) {
-      tile_trsm<W, CP, false>(eye_r, eye_i, tri_l, rdiag, w, [&](int i, int col, double2 x) {
+      tile_trsm<W, false>(eye, tri_l, rdiag, w, [&](int i, int col, double2 x) {
         if (col < w) dst[i * W + col] = x;
       });
-      tile_trsm<W, CP, true>(eye_r, eye_i, tri_u, rdiag, w, [&](int i, int col, double2 x) {
+      tile_trsm<W, true>(eye, tri_u, rdiag, w, [&](int i, int col, double2 x) {
         if (col < w) dst[W * W + i * W + col] = x;
       });
     }
@@ -723,7 +675,8 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int rows, i
     }
   }
   __syncthreads();
-  tile_trsm<W, CP, kUpper>(cr, ci, tri, rdiag, w, [&](int i, int col, double2 v) {
+  tile_trsm<W, kUpper>([&](int i, int col) { return make_double2(cr[i * CP + col], ci[i * CP + col]); }, tri, rdiag, w,
+                       [&](int i, int col, double2 v) {
     if (c0 + col < c_hi) cv.p[(long)sp[i] * cv.ld + c0 + col] = v;
   });
 }
