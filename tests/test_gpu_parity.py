@@ -158,10 +158,11 @@ def test_chain_crystal_all_energies(ctx):
         assert abs(out["T"][b, 0] - ref["t_lr"]) <= TOL * max(1.0, ref["t_lr"])
 
 
-@pytest.mark.parametrize("n,nmat", [(1, 2), (33, 3), (100, 2), (512, 3), (700, 2), (1100, 1)])
+@pytest.mark.parametrize("n,nmat", [(1, 2), (33, 3), (84, 2), (100, 2), (250, 2), (512, 3), (700, 2), (1100, 1)])
 def test_lu_factor_vs_oracle(ctx, n, nmat):
     """The batched LU (panel widths 32, 16 and 8 by order) takes the oracle's pivots exactly and its
-    factors agree element by element (rounding-order differences only)."""
+    factors agree element by element (rounding-order differences only).  Orders 84 and 250 end in
+    panels of 20 and 26 columns: full and partial 8-column quarters."""
     import paper_1812_01396_amd as ss
     print(f"lu_factor n={n} nmat={nmat}", flush=True)
     rng = np.random.default_rng(n + nmat)
