@@ -20,11 +20,11 @@
 
 namespace ss {
 
-int lu_panel_width(int n) { return n <= 512 ? 32 : (n <= 1024 ? 16 : 8); }
+int lu_panel_width(int n) { return n <= 1024 ? 32 : 8; }
 
 bool lu_panel_width_ok(int n, int w) {
-  // a panel keeps R rows per thread in one workgroup: W 32 (R 1, 512 threads), 16 (R 1, 1024), 8 (R 2, 1024)
-  return (w == 32 && n <= 512) || (w == 16 && n <= 1024) || (w == 8 && n <= 2048);
+  // a panel keeps R rows per thread in one workgroup: W 32 and 16 (R 1, up to 1024 threads), 8 (R 2, 1024)
+  return (w == 32 && n <= 1024) || (w == 16 && n <= 1024) || (w == 8 && n <= 2048);
 }
 
 static int panel_width(const ss_ctx *ctx, int n) {
@@ -365,7 +365,7 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
 
 // ------------------------------------------------------------------ 32-column panel in quarters
 
-// The 32-column panel (n <= 512, one logical row per thread) in four quarters of 8 columns.  Quarter q is
+// The 32-column panel (n <= 1024, one logical row per thread) in four quarters of 8 columns.  Quarter q is
 // loaded, receives the updates of the 8q columns before it (first the rows of their pivots, in pivot
 // order, then every row below them as one product with those rows), and is factored with its columns
 // unrolled, then written back.  Every element receives the updates of a one-pass panel in the same
@@ -373,7 +373,8 @@ __global__ void __launch_bounds__(LB) k_panel(LuArgs a, int c0) {
 // of its row instead of 32: the workgroup needs about a quarter of a CU's register file and shares the CU
 // with other work, where a whole row per thread needs all of it.  Also leaves the inverses of the
 // diagonal block's triangles.
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k_panel32(LuArgs a, int c0) {
+template <int LB>
+__global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(6))) k_panel32(LuArgs a, int c0) {
   constexpr int W = 32, H = 8, NQ = W / H;
   const int mat = blockIdx.x;
   if (skipped(a, mat)) return;
@@ -384,11 +385,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6))) k
   const int w = min(W, nrows);
   const long ld = a.ldm;
 
-  __shared__ int sperm[512];
+  __shared__ int sperm[LB];
   __shared__ double2 tri_l[W][W + 1], tri_u[W][W + 1];
   __shared__ double2 rdiag[W];
-  __shared__ double red_v[8];
-  __shared__ int red_i[8];
+  __shared__ double red_v[LB / 64];
+  __shared__ int red_i[LB / 64];
   __shared__ double2 rowbuf[2][H];
   __shared__ double2 ub[W - H][H];          // the quarter's part of the earlier pivot rows (final)
   __shared__ double2 lt[W - H][W - H + 1];  // multipliers among the earlier pivot rows
@@ -949,10 +950,14 @@ struct LuRun {
       // at least four waves: they invert the panel's diagonal block at the end
       const int threads = std::min(LB, std::max(256, cdiv(rows, 64) * 64));
       KernelScope ks_(ctx, "panel");
-      if constexpr (W == 32 && R == 1 && LB == 512)
-        hipLaunchKernelGGL(k_panel32, dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
-      else
+      if constexpr (W == 32 && R == 1) {
+        if (threads <= 512)
+          hipLaunchKernelGGL(k_panel32<512>, dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+        else
+          hipLaunchKernelGGL(k_panel32<1024>, dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+      } else {
         hipLaunchKernelGGL((k_panel<W, R, LB>), dim3(d.nmat), dim3(threads), 0, ctx->stream, a, c0);
+      }
       return;
     }
     const int cm = mid(c0, c1);
@@ -988,7 +993,7 @@ ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   // the panels keep the inverses of their diagonal blocks for the triangular-solve leaves
   a.sInv = (long)cdiv(d.n, W) * 2 * W * W;
   SS_TRY(workspace(ctx, kSlotLuInv, sizeof(double2) * (size_t)d.nmat * a.sInv, (void **)&a.inv));
-  if (W == 32) return LuRun<32, 1, 512>{ctx, d, a}.run();
+  if (W == 32) return LuRun<32, 1, 1024>{ctx, d, a}.run();
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, a}.run();
   return LuRun<8, 2, 1024>{ctx, d, a}.run();
 }
@@ -997,7 +1002,7 @@ ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_apply: order out of range");
   const int W = panel_width(ctx, d.n);
-  if (W == 32) return LuRun<32, 1, 512>{ctx, d, make_args(d)}.run(false);
+  if (W == 32) return LuRun<32, 1, 1024>{ctx, d, make_args(d)}.run(false);
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run(false);
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run(false);
 }

@@ -32,8 +32,8 @@ struct LuDesc {
   int ldb = 0;
 };
 
-// Default panel width of the factorization for order n (32 up to n = 512, 16 up to 1024, 8 up to
-// 2048); a context may ask for another width (ss_ctx::lu_width) where lu_panel_width_ok allows it.
+// Default panel width of the factorization for order n (32 up to n = 1024, 8 up to 2048); a context
+// may ask for another width (ss_ctx::lu_width) where lu_panel_width_ok allows it.
 int lu_panel_width(int n);
 bool lu_panel_width_ok(int n, int w);
 // Largest order supported.
