@@ -753,63 +753,95 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
   Lds<T> L(lds);
   constexpr int E = H * H / T::NT;         // elements per thread of a 32 x 32 operand
   constexpr int EB = H * T::BN / T::NT;   // elements per thread of 32 right-hand-side rows
-  // A operand (r, k) -> planes [k][r];  B operand (k, c) -> planes [k][c]
-  auto stage_a = [&](auto load) {
-    double2 v[E];
+  // A operand (r, k) -> planes [k][r];  B operand (k, c) -> planes [k][c].  Every operand that does not
+  // depend on this workgroup's results is fetched into registers one stage ahead, while the matrix cores
+  // work on the current stage, and stored to LDS after the next barrier.
+  double2 pa[E], pb[EB], pc[4 * T::FM * T::FN];
+  auto fetch_a = [&](auto load) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) v[e] = load((tid + e * T::NT) / H, (tid + e * T::NT) % H);
+    for (int e = 0; e < E; ++e) pa[e] = load((tid + e * T::NT) / H, (tid + e * T::NT) % H);
+  };
+  auto put_a = [&]() {
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       const int r = (tid + e * T::NT) / H, k = (tid + e * T::NT) % H;
-      L.ar[k * T::PA + r] = v[e].x;
-      L.ai[k * T::PA + r] = v[e].y;
+      L.ar[k * T::PA + r] = pa[e].x;
+      L.ai[k * T::PA + r] = pa[e].y;
     }
   };
-  auto stage_b_rows = [&](const int *rowmap) {  // 32 right-hand-side rows (columns n0 .. n0 + BN - 1)
-    double2 v[EB];
+  auto fetch_b_rows = [&](const int *rowmap) {  // 32 right-hand-side rows (columns n0 .. n0 + BN - 1)
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int k = (tid + e * T::NT) / T::BN, c = (tid + e * T::NT) % T::BN;
-      v[e] = n0 + c < c_hi ? cv.p[(long)rowmap[k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+      pb[e] = n0 + c < c_hi ? cv.p[(long)rowmap[k] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
     }
+  };
+  auto put_b = [&]() {
 #pragma unroll
     for (int e = 0; e < EB; ++e) {
       const int k = (tid + e * T::NT) / T::BN, c = (tid + e * T::NT) % T::BN;
-      L.br[k * T::PB + c] = v[e].x;
-      L.bi[k * T::PB + c] = v[e].y;
+      L.br[k * T::PB + c] = pb[e].x;
+      L.bi[k * T::PB + c] = pb[e].y;
     }
   };
-  // B planes <- C_half - acc (C read from memory in the accumulator's element order)
-  auto publish_diff = [&](const Acc<T> &acc, int half) {
+  // C of a half (its right-hand-side rows), in the accumulator's element order
+  auto fetch_c = [&](int half) {
+    Acc<T> shape;
+    int i = 0;
+    acc_foreach<T>(shape, [&](int r, int c, double2) {
+      pc[i++] = n0 + c < c_hi ? cv.p[(long)sp[half + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
+    });
+  };
+  // B planes <- C - acc
+  auto publish_diff = [&](const Acc<T> &acc) {
+    int i = 0;
     acc_foreach<T>(acc, [&](int r, int c, double2 x) {
-      const double2 ch = n0 + c < c_hi ? cv.p[(long)sp[half + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
-      L.br[r * T::PB + c] = ch.x - x.x;
-      L.bi[r * T::PB + c] = ch.y - x.y;
+      L.br[r * T::PB + c] = pc[i].x - x.x;
+      L.bi[r * T::PB + c] = pc[i].y - x.y;
+      ++i;
     });
   };
   auto coupling = [&](int half, int col0) {  // factors' block at rows r0 + half, columns col0
     return [=](int r, int k) { return M[(long)sp[half + r] * a.ldm + col0 + k]; };
   };
+  auto inv_of = [&](const double2 *iv) {
+    return [=](int r, int k) { return iv[r * H + k]; };
+  };
   Acc<T> acc_f, acc_g;
   acc_f.zero();
   acc_g.zero();
   if (p0 >= 0) {  // F X_p for both halves, in two 32-deep steps
+    fetch_b_rows(spp);
+    fetch_a(coupling(f, p0));
+#pragma unroll
     for (int kk = 0; kk < 2; ++kk) {
-      stage_b_rows(spp + kk * H);
-      stage_a(coupling(f, p0 + kk * H));
+      put_b();
+      put_a();
       __syncthreads();
+      fetch_a(coupling(g, p0 + kk * H));
       mma_stage<T>(L, acc_f);
       __syncthreads();
-      stage_a(coupling(g, p0 + kk * H));
+      put_a();
       __syncthreads();
+      if (kk == 0) {
+        fetch_b_rows(spp + H);
+        fetch_a(coupling(f, p0 + H));
+      } else {
+        fetch_c(f);
+        fetch_a(inv_of(inv_f));
+      }
       mma_stage<T>(L, acc_g);
       __syncthreads();
     }
+  } else {
+    fetch_c(f);
+    fetch_a(inv_of(inv_f));
   }
   // ---- X_f = inv_f (C_f - acc_f)
-  publish_diff(acc_f, f);
-  stage_a([&](int r, int k) { return inv_f[r * H + k]; });
+  publish_diff(acc_f);
+  put_a();
   __syncthreads();
+  fetch_a(coupling(g, r0 + f));
   Acc<T> acc;
   acc.zero();
   mma_stage<T>(L, acc);
@@ -823,13 +855,15 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
     L.bi[r * T::PB + c] = x.y;
   });
   // ---- Y = C_g - acc_g - coupling X_f   (coupling: L21 below the first half, U12 right of the second)
-  stage_a(coupling(g, r0 + f));
+  put_a();
   __syncthreads();
+  fetch_c(g);
+  fetch_a(inv_of(inv_g));
   mma_stage<T>(L, acc_g);
   __syncthreads();
-  publish_diff(acc_g, g);
+  publish_diff(acc_g);
   // ---- X_g = inv_g Y
-  stage_a([&](int r, int k) { return inv_g[r * H + k]; });
+  put_a();
   __syncthreads();
   acc.zero();
   mma_stage<T>(L, acc);
