@@ -17,6 +17,8 @@
 namespace ss {
 
 using ObcTile = TileCfg<64, 64, 16, 2, 2>;
+// psi = Q (b' + z) has as many columns as injected modes (typically 32): a 64 x 32 tile of four waves
+using PsiTile = TileCfg<64, 32, 16, 4, 1>;
 
 // element (r, k) of Q_c = [Q_{1,:}; Q_{nb,:}] (2s x 2s) from Q [nb*s][2s]
 struct LdCorner {
@@ -142,8 +144,8 @@ __global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_gc(ObcArgs a)
 }
 
 // psi = Q (b' + z): rows nb*s, columns m, depth 2s
-__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_psi(ObcArgs a) {
-  using T = ObcTile;
+__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES k_obc_psi(ObcArgs a) {
+  using T = PsiTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;
   const int rows = obc_nb(a, inst) * s;
@@ -214,8 +216,8 @@ static ss_status obc_run(ss_ctx *ctx, ObcArgs &a, int nb_max, bool want_psi, int
   }
   if (m > 0 && want_psi) {
     KernelScope ks_(ctx, "obc");
-    hipLaunchKernelGGL(k_obc_psi, dim3(cdiv(nb_max * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0,
-                       ctx->stream, a);
+    hipLaunchKernelGGL(k_obc_psi, dim3(cdiv(nb_max * s, PsiTile::BM) * cdiv(m, PsiTile::BN), batch),
+                       dim3(PsiTile::NT), 0, ctx->stream, a);
   }
   hipLaunchKernelGGL(k_obc_info, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const int *)wZ, info, batch);
   return check_launch(ctx, "apply_obc");
