@@ -571,6 +571,9 @@ __global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(6))) k_
 using LuTile = TileCfg<64, 64, 16, 2, 2>;
 // products of at most 32 rows (the deepest levels of the triangular solves): one row of four waves
 using LuTileFlat = TileCfg<32, 128, 16, 1, 4>;
+// products of at most 32 columns (the depth-32 trailing updates inside a 64-column block): one column
+// of four waves, no padded half tile
+using LuTileNarrow = TileCfg<64, 32, 16, 4, 1>;
 
 // the row map into LDS (n <= kLuMaxN, 256 threads): all loads are issued before the first store
 __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
@@ -908,6 +911,10 @@ struct LuRun {
       const int tiles = cdiv(c_hi - c_lo, LuTileFlat::BN);
       hipLaunchKernelGGL(k_lu_gemm<LuTileFlat>, dim3(tiles, d.nmat), dim3(LuTileFlat::NT), 0, ctx->stream, a, r_lo,
                          r_hi, c_lo, c_hi, k_lo, k_hi);
+    } else if (c_hi - c_lo <= LuTileNarrow::BN && r_hi - r_lo > LuTileNarrow::BM) {
+      const int tiles = cdiv(r_hi - r_lo, LuTileNarrow::BM);
+      hipLaunchKernelGGL(k_lu_gemm<LuTileNarrow>, dim3(tiles, d.nmat), dim3(LuTileNarrow::NT), 0, ctx->stream, a,
+                         r_lo, r_hi, c_lo, c_hi, k_lo, k_hi);
     } else {
       const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
       hipLaunchKernelGGL(k_lu_gemm<LuTile>, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi,
