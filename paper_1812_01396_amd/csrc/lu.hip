@@ -689,10 +689,10 @@ __global__ void __launch_bounds__(256) k_trsm_leaf(LuArgs a, int r0, int rows, i
 // replaced by T^{-1} times themselves, with T^{-1} the inverse of the W x W diagonal block at logical
 // row/column r0 (unit lower if !kUpper, upper otherwise) kept by its panel; r0 is a multiple of W.
 // Every workgroup reads all w rows of its columns before it writes them, so the update is in place.
-template <bool kUpper>
-__global__ void __launch_bounds__(LuTileFlat::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W, int r0, int rows,
-                                                                           int c_lo, int c_hi, int to_x) {
-  using T = LuTileFlat;
+template <bool kUpper, class T>
+__global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W, int r0, int rows, int c_lo,
+                                                                  int c_hi, int to_x) {
+  static_assert(T::BM == 32 && T::NT >= T::BM, "leaf tile: up to 32 rows");
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ int sp[T::BM];
   const int mat = blockIdx.y;
@@ -929,9 +929,12 @@ struct LuRun {
   void leaf(int r0, int rows, int c_lo, int c_hi) {
     if (c_lo >= c_hi) return;
     KernelScope ks_(ctx, "trsm");
-    if (a.inv != nullptr)
-      hipLaunchKernelGGL(k_lu_leaf<kUpper>, dim3(cdiv(c_hi - c_lo, LuTileFlat::BN), d.nmat), dim3(LuTileFlat::NT), 0,
-                         ctx->stream, a, W, r0, rows, c_lo, c_hi, kUpper ? to_x : 0);
+    if (a.inv != nullptr && c_hi - c_lo <= LuTileLeaf::BN)  // a narrow range: no padded 128-wide tile
+      hipLaunchKernelGGL((k_lu_leaf<kUpper, LuTileLeaf>), dim3(cdiv(c_hi - c_lo, LuTileLeaf::BN), d.nmat),
+                         dim3(LuTileLeaf::NT), 0, ctx->stream, a, W, r0, rows, c_lo, c_hi, kUpper ? to_x : 0);
+    else if (a.inv != nullptr)
+      hipLaunchKernelGGL((k_lu_leaf<kUpper, LuTileFlat>), dim3(cdiv(c_hi - c_lo, LuTileFlat::BN), d.nmat),
+                         dim3(LuTileFlat::NT), 0, ctx->stream, a, W, r0, rows, c_lo, c_hi, kUpper ? to_x : 0);
     else
       hipLaunchKernelGGL((k_trsm_leaf<TL, kUpper>), dim3(cdiv(c_hi - c_lo, 64), d.nmat), dim3(256), 0, ctx->stream,
                          a, r0, rows, c_lo, c_hi);
