@@ -69,6 +69,12 @@ ss_status ss_set_stream(ss_ctx *ctx, void *hip_stream);
  * Workspaces must already be large enough (run the same calls once eagerly first): growing a
  * workspace waits for the stream, and the call then fails with SS_ERR_ARG instead. */
 ss_status ss_set_sync_free(ss_ctx *ctx, int on);
+/* Panel width of this context's batched LU factorizations (the recursion of Sec. 3B bottoms out in
+ * panels of `width` columns): 0 restores the default by order (32 up to n = 1024, 8 up to 2048); 32 or
+ * 16 apply up to n = 1024 and 8 up to n = 2048, and an order outside a width's range uses the default.
+ * Results agree to rounding for every width.  SS_ERR_ARG for any other value.  A plan sets the width of
+ * each of its groups itself. */
+ss_status ss_set_lu_width(ss_ctx *ctx, int width);
 /* Block the host until the context's stream has drained. */
 ss_status ss_synchronize(ss_ctx *ctx);
 /* Static text for a status code, and the detail of the context's last failure ("" if none). */

@@ -147,6 +147,14 @@ ss_status ss_set_sync_free(ss_ctx *ctx, int on) {
   return SS_OK;
 }
 
+ss_status ss_set_lu_width(ss_ctx *ctx, int width) {
+  if (!ctx) return SS_ERR_ARG;
+  if (width != 0 && width != 32 && width != 16 && width != 8)
+    return ss::fail(ctx, SS_ERR_ARG, "ss_set_lu_width: width must be 0, 32, 16 or 8");
+  ctx->lu_width = width;
+  return SS_OK;
+}
+
 ss_status ss_synchronize(ss_ctx *ctx) {
   SS_TRY(enter(ctx));
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");

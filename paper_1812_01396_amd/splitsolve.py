@@ -22,7 +22,7 @@ SS_PREC_FP64, SS_PREC_FP32 = 0, 1
 SS_KEEP_FACTORS = 1
 
 EXPORTS = (
-    "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_synchronize", "ss_status_string", "ss_last_error",
+    "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_set_lu_width", "ss_synchronize", "ss_status_string", "ss_last_error",
     "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
@@ -85,6 +85,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_set_stream.restype = I
     lib.ss_set_sync_free.argtypes = [P, I]
     lib.ss_set_sync_free.restype = I
+    lib.ss_set_lu_width.argtypes = [P, I]
+    lib.ss_set_lu_width.restype = I
     lib.ss_synchronize.argtypes = [P]
     lib.ss_synchronize.restype = I
     lib.ss_status_string.argtypes = [I]
@@ -214,6 +216,10 @@ class Context:
     def set_sync_free(self, on: bool):
         """Never wait for the stream inside a call (for stream/graph capture)."""
         self.check(self.lib.ss_set_sync_free(self.handle, int(bool(on))))
+
+    def set_lu_width(self, width: int):
+        """LU panel width for this context's factorizations (0: the default by order)."""
+        self.check(self.lib.ss_set_lu_width(self.handle, int(width)))
 
     def synchronize(self):
         self.check(self.lib.ss_synchronize(self.handle))

@@ -177,6 +177,35 @@ def test_lu_factor_vs_oracle(ctx, n, nmat):
         assert np.abs(lu[b] - ref).max() <= 1e-11 * np.abs(ref).max(), (b, np.abs(lu[b] - ref).max())
 
 
+@pytest.mark.parametrize("width,n", [(16, 100), (16, 512), (16, 700), (8, 250), (8, 512), (32, 512)])
+def test_lu_factor_panel_widths(ctx, width, n):
+    """Every panel width a context (or a plan's autotuner) can choose gives the oracle's pivots and
+    factors: 16-column panels with whole rows in registers, 8-column panels with two rows per thread."""
+    import paper_1812_01396_amd as ss
+    print(f"lu_factor width={width} n={n}", flush=True)
+    rng = np.random.default_rng(width * 1000 + n)
+    a = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    ctx.set_lu_width(width)
+    try:
+        lu, perm, info = ss.ss_lu_factor(ctx, _dev(a))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_lu_width(0)
+    lu, perm, info = lu.cpu().numpy(), perm.cpu().numpy(), info.cpu().numpy()
+    for b in range(2):
+        ref, rperm, rinfo = linalg.lu_partial_pivot(a[b])
+        assert info[b] == rinfo == 0
+        assert np.array_equal(perm[b], rperm), (b, int(np.argmax(perm[b] != rperm)))
+        assert np.abs(lu[b] - ref).max() <= 1e-11 * np.abs(ref).max(), (b, np.abs(lu[b] - ref).max())
+
+
+def test_lu_width_rejects_other_values(ctx):
+    import paper_1812_01396_amd as ss
+    for bad in (-1, 4, 24, 64):
+        with pytest.raises(ss.splitsolve.SplitSolveError):
+            ctx.set_lu_width(bad)
+
+
 def test_lu_factor_zero_pivots(ctx):
     import paper_1812_01396_amd as ss
     rng = np.random.default_rng(9)
