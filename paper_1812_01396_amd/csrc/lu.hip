@@ -789,7 +789,8 @@ __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuAr
   };
   // C of a half (its right-hand-side rows), in the accumulator's element order
   auto fetch_c = [&](int half) {
-    Acc<T> shape;
+    Acc<T> shape;  // only its element positions are used
+    shape.zero();
     int i = 0;
     acc_foreach<T>(shape, [&](int r, int c, double2) {
       pc[i++] = n0 + c < c_hi ? cv.p[(long)sp[half + r] * cv.ld + n0 + c] : make_double2(0.0, 0.0);
