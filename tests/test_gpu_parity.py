@@ -64,6 +64,32 @@ def test_precompute_columns_vs_oracle(ctx, nb, s):
         assert _rel(q[b], ref) <= TOL, (b, _rel(q[b], ref))
 
 
+@pytest.mark.parametrize("width", [16, 8])
+def test_precompute_columns_panel_widths(ctx, width):
+    """Alg. 1 with the narrower LU panels (substitution-free matrix-core leaves of 16 or 8 rows instead of
+    the fused 64-row ones) agrees with the oracle as the default width does."""
+    import paper_1812_01396_amd as ss
+    nb, s = 3, 130
+    print(f"precompute width={width} nb={nb} s={s}", flush=True)
+    insts = [synth.random_btd(nb, s, seed=2000 + width + k) for k in range(2)]
+    Es = np.array([0.21, -0.38])
+    kidx = np.array([0, 1], dtype=np.int32)
+    hd, hu, sd, su = _stack_sets(insts)
+    ctx.set_lu_width(width)
+    try:
+        q, info = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), _dev(Es, torch.float64),
+                                           kidx=_dev(kidx, torch.int32))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_lu_width(0)
+    q = q.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    for b, (E, k) in enumerate(zip(Es, kidx)):
+        ad, au, al = transport.device_blocks(insts[k].Hd, insts[k].Hu, insts[k].Sd, insts[k].Su, E)
+        ref = transport.first_last_columns(ad, au, al)
+        assert _rel(q[b], ref) <= TOL, (b, _rel(q[b], ref))
+
+
 def test_precompute_columns_zero_pivot_code(ctx):
     """A decoupled device with E on an onsite level: exactly zero pivots, reported LAPACK-style."""
     import paper_1812_01396_amd as ss
