@@ -23,7 +23,7 @@ Workloads (synthetic, seeded; see synth/):
            of [0, pi)) and evaluated on 2048 held-out points: cold decimation vs warm start (network +
            Newton + judge + fallback) vs continuation from the nearest training point
 
-Prints one JSON line.  --gpus > 1 is refused: this build measures one GPU.
+Prints one JSON line.  --gpus > 1 is refused: the benchmark measures one GPU.
 """
 from __future__ import annotations
 
@@ -615,7 +615,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: run with --gpus 1 (this build has no multi-GPU path)",
+        print("bench.py measures one GPU only: run with --gpus 1 (the library has no multi-GPU path)",
               file=sys.stderr)
         sys.exit(2)
 

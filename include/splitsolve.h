@@ -49,7 +49,7 @@ typedef enum {
   SS_ERR_ARG = 1,         /* invalid argument (null pointer, size out of range)            */
   SS_ERR_NOMEM = 2,       /* device workspace allocation failed                             */
   SS_ERR_DEVICE = 3,      /* a HIP runtime call failed (launch, copy, synchronization)      */
-  SS_ERR_UNSUPPORTED = 4  /* a well-formed request outside what this build implements       */
+  SS_ERR_UNSUPPORTED = 4  /* a well-formed request outside what the library implements     */
 } ss_status;
 
 /* Largest block size accepted (the 2s x 2s corner system needs 2s <= 2048). */
