@@ -158,12 +158,25 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
  * with partial pivoting on the GPU.  prec: SS_PREC_FP64 or SS_PREC_FP32 (see above); flags: 0 or
  * SS_KEEP_FACTORS.
  *
- * Output Q [batch][nb][s][2s]: block row i holds (A^{-1})_{i,1} in columns [0, s) and
- * (A^{-1})_{i,n_B} in columns [s, 2s).  info [batch] (may be NULL): 0, or 1 + (i-1)*s + c for an
+ * absorb (>= 0, finite): absorbing boundary.  The open system is T = A - B C with B the identity blocks
+ * at the top and bottom and C holding the self-energies (Sec. 3B, Eq. (x)); the section leaves the
+ * choice of B and C free.  With absorb > 0 the constant part -i*absorb*I of both self-energies is
+ * moved from C into A: the first and last diagonal blocks are formed as E*S - H + i*absorb*I (the
+ * single block gets 2i*absorb*I when nb == 1), Q is the first and last block columns of that A'^{-1},
+ * and ss_apply_obc must be given the same absorb (it then uses C' = Sigma + i*absorb*I, so that
+ * A' - B C' = T).  The pre-processing still needs no self-energy.  Alg. 1 pivots only inside blocks;
+ * its pivot blocks are Schur complements of closed sub-chains of the device, nearly singular wherever
+ * E approaches one of their eigenvalues, and the closed A itself is singular at the device's
+ * eigenvalues; the absorber broadens all of these resonances, which keeps the digits that the closed
+ * recursion and the correction otherwise lose.  absorb = 0 is the paper's A = E*S - H.
+ *
+ * Output Q [batch][nb][s][2s]: block row i holds (A'^{-1})_{i,1} in columns [0, s) and
+ * (A'^{-1})_{i,n_B} in columns [s, 2s).  info [batch] (may be NULL): 0, or 1 + (i-1)*s + c for an
  * exactly zero pivot in column c of the i-th diagonal system (1-based i; the smallest such code over
  * both recursions). */
 ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx,
-                                const double *E, int prec, int flags, ss_c128 *Q, int *info);
+                                const double *E, double absorb, int prec, int flags, ss_c128 *Q,
+                                int *info);
 
 /* The block solver of Step 1 on its own: batched LU with partial pivoting (Alg. 1 solves every
  * D_i X_i = A_{i,i+1} through this factorization).
@@ -178,7 +191,8 @@ ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int 
 
 /* Steps 2-4 (Sec. 3B, Eq. (x)): fold the boundary self-energies in and recover the wave function.
  *
- * With C Q = [Sigma_L Q_{1,:}; Sigma_R Q_{n_B,:}] (2s x 2s), R = I - C Q, b' = inj (the non-zero
+ * With C Q = [Sigma'_L Q_{1,:}; Sigma'_R Q_{n_B,:}] (2s x 2s), Sigma' = Sigma + i*absorb*I (absorb as
+ * given to ss_precompute_columns for this Q; 0: Sigma' = Sigma), R = I - C Q, b' = inj (the non-zero
  * rows of Inj: first block row on top, last block row below) and z = R^{-1} (C Q) b':
  *     psi = Q (b' + z)                      [batch][nb][s][m]
  *     gc  = [Q_{1,:}; Q_{n_B,:}] R^{-1}     [batch][2s][2s]: the corner blocks
@@ -187,7 +201,7 @@ ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int 
  * gc may be NULL.  info [batch] (may be NULL): 0, or 1 + c for an exactly zero pivot in column c
  * of R. */
 ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q,
-                       const ss_c128 *sigma, int m, const ss_c128 *inj, ss_c128 *psi,
+                       const ss_c128 *sigma, double absorb, int m, const ss_c128 *inj, ss_c128 *psi,
                        ss_c128 *gc, int *info);
 
 /* Caroli transmission from the corner of G^R (the product the hot path ends with):
@@ -211,7 +225,9 @@ ss_status ss_injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma,
  *     r = B b' - (A - B C) psi   (FP64),   psi += A~^{-1} r + Q R^{-1} C A~^{-1} r,
  * where A~^{-1} uses the factors kept by the last ss_precompute_columns(..., SS_KEEP_FACTORS) on this
  * context (the same hs, batch, kidx and E) and R^{-1} the corner factorization of the last
- * ss_apply_obc on this context (no other call may run on the context in between).  Stops per instance
+ * ss_apply_obc on this context (no other call may run on the context in between).  With an absorbing
+ * boundary both calls must have used the same absorb (SS_ERR_ARG otherwise); A~ and C are then A' and
+ * C' = Sigma + i*absorb*I, while the residual is always that of A - Sigma.  Stops per instance
  * when ||r||_F <= tol ||B b'||_F (tol <= 0 means 1e-12) or after max_iter passes (<= 0 means 10).
  * psi [batch][nb][s][m] is updated in place; iters [batch] and resid [batch] (final relative
  * residual) may be NULL. */
@@ -298,6 +314,8 @@ typedef struct {
 
 typedef struct {
   double eta;        /* broadening of the lead's diagonal cell (>= 0) */
+  double absorb;     /* absorbing boundary of Step 1 and the corner correction (>= 0; see
+                        ss_precompute_columns) */
   double sigma_tol;  /* decimation tolerance (0: 1e-14) */
   int sigma_passes;  /* decimation passes enqueued (0: ceil(log2(1/eta)) + 12, within [16, 200]);
                         converged instances skip later passes, unconverged ones report info -1 */

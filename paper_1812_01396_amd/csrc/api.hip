@@ -1,4 +1,5 @@
 // C ABI entry points: argument validation, context and workspace management.
+#include <cmath>
 #include <cstdio>
 #include <new>
 
@@ -217,7 +218,7 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
 }
 
 ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
-                                int prec, int flags, ss_c128 *Q, int *info) {
+                                double absorb, int prec, int flags, ss_c128 *Q, int *info) {
   SS_TRY(enter(ctx));
   if (!hs) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null structure");
   if (batch < 0 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
@@ -229,8 +230,10 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown precision");
   if (flags & ~SS_KEEP_FACTORS) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown flags");
+  if (!(absorb >= 0.0) || !std::isfinite(absorb))
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: absorb must be finite and >= 0");
   ctx->corner_valid = false;  // the recursion reuses the corner system's workspace
-  return precompute_columns(ctx, hs, batch, kidx, E, prec, flags, Q, info);
+  return precompute_columns(ctx, hs, batch, kidx, E, absorb, prec, flags, Q, info);
 }
 
 ss_status ss_measure_ceilings(ss_ctx *ctx, double *ceil) {
@@ -249,16 +252,19 @@ ss_status ss_lu_factor(ss_ctx *ctx, int nmat, int n, ss_c128 *A, int *perm, int 
   return lu_factor_dense(ctx, nmat, n, (double2 *)A, perm, info);
 }
 
-ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                       const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, double absorb,
+                       int m, const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
   SS_TRY(enter(ctx));
   if (batch < 0 || nb < 1 || s < 1 || m < 0) return fail(ctx, SS_ERR_ARG, "ss_apply_obc: size out of range");
   if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_apply_obc: s > SS_MAX_S");
   if (batch == 0) return SS_OK;
   if (!Q || !sigma || (m > 0 && (!inj || !psi)))
     return fail(ctx, SS_ERR_ARG, "ss_apply_obc: null input or output pointer");
-  ss_status st = apply_obc(ctx, batch, nb, s, Q, sigma, m, inj, psi, gc, info);
+  if (!(absorb >= 0.0) || !std::isfinite(absorb))
+    return fail(ctx, SS_ERR_ARG, "ss_apply_obc: absorb must be finite and >= 0");
+  ss_status st = apply_obc(ctx, batch, nb, s, Q, sigma, absorb, m, inj, psi, gc, info);
   ctx->corner_valid = st == SS_OK;
+  ctx->corner_absorb = absorb;
   ctx->corner_batch = batch;
   ctx->corner_s = s;
   ctx->corner_ldm = 4 * s + m;

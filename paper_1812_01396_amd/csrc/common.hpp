@@ -99,8 +99,10 @@ struct ss_ctx {
   // what the kept workspaces currently describe (for ss_refine_psi)
   bool fact_valid = false;   // kSlotX + kSlotFact/FactPerm hold a first-column recursion
   int fact_batch = 0, fact_nb = 0, fact_s = 0;
+  double fact_absorb = 0.0;  // absorbing shift of the boundary blocks the kept factors were formed with
   bool corner_valid = false;  // kSlotM/kSlotPerm hold the factored corner systems of ss_apply_obc
   int corner_batch = 0, corner_s = 0, corner_ldm = 0;
+  double corner_absorb = 0.0;  // the shift in C' = Sigma + i*absorb*I of the factored corner systems
   // kernel timing probe: launches of `timer_family` are bracketed by event pairs
   std::string timer_family;
   std::vector<hipEvent_t> timer_events;

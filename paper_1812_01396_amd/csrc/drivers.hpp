@@ -20,22 +20,22 @@ struct RaggedBatch {
   std::vector<int> act;
 };
 
-ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, int prec, ss_c128 *Q, int *info);
+ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, double absorb, int prec, ss_c128 *Q, int *info);
 
-ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
-                             int flags, ss_c128 *Q, int *info);
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                             double absorb, int prec, int flags, ss_c128 *Q, int *info);
 
 ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
                           const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,
                           double eta, double tol, int max_iter, ss_c128 *sigma, int *iters,
                           double *resid, int *info, const ss_c128 *const *tab = nullptr);
 
-ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info);
+ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, double absorb,
+                    int m, const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info);
 // The same for a ragged batch (Q packed as by precompute_ragged); psi_tab: per-instance destinations
 // [nb(i)][s][m] of psi (null entries or a null table: psi is not formed).
-ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                           const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info);
+ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q, const ss_c128 *sigma, double absorb,
+                           int m, const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info);
 
 ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T);
 

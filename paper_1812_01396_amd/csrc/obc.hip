@@ -5,6 +5,9 @@
 //     R   = I - C Q,   [V | z] = R^{-1} [I | C Q b']           (one LU solve, 2s + m right-hand sides)
 //     gc  = [Q_{1,:}; Q_{nb,:}] V                               (corner of G^R = (A - B C)^{-1} = Q R^{-1})
 //     psi = Q (b' + z)                                          (y + Q z with y = Q b')
+// With an absorbing boundary (absorb > 0, see sweep.hip) Q = A'^{-1} B for A' = A + i*absorb*[boundary
+// blocks], and every C above is C' = C + i*absorb*I (T = A - B C = A' - B C'), so C Q gains
+// i*absorb*[Q_{1,:}; Q_{nb,:}].
 // The transmission uses only the off-diagonal corner blocks:
 //     T_LR = Re Tr[Gamma_L G_1n Gamma_R G_1n^H] = Re sum_ij (Gamma_L G_1n)_ij conj((G_1n Gamma_R)_ij)
 // (Gamma Hermitian), and likewise T_RL with G_n1 and the leads exchanged.
@@ -56,6 +59,7 @@ struct LdGamma {
 struct ObcArgs {
   const double2 *Q, *sigma, *inj;
   double2 *psi, *gc;
+  double absorb;  // C' = Sigma + i*absorb*I
   int nb, s, m, batch;
   const int *nbv;               // per-instance block counts (null: nb)
   const long *boff;             // first block of each instance in the packed Q (null: inst * nb)
@@ -94,6 +98,10 @@ __global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cq(ObcArgs a)
   acc_foreach<T>(acc, [&](int r, int c, double2 v) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < s && gc < 2 * s) {
+      if (a.absorb != 0.0) {  // + i*absorb*Q_row
+        const double2 q = qrow[(long)gr * 2 * s + gc];
+        v = make_double2(v.x - a.absorb * q.y, v.y + a.absorb * q.x);
+      }
       const int row = half * s + gr;
       const double d = row == gc ? 1.0 : 0.0;
       cq[(long)row * 2 * s + gc] = v;
@@ -223,11 +231,12 @@ static ss_status obc_run(ss_ctx *ctx, ObcArgs &a, int nb_max, bool want_psi, int
   return check_launch(ctx, "apply_obc");
 }
 
-ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                    const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
+ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, const ss_c128 *sigma, double absorb,
+                    int m, const ss_c128 *inj, ss_c128 *psi, ss_c128 *gc, int *info) {
   ObcArgs a{};
   a.Q = (const double2 *)Q;
   a.sigma = (const double2 *)sigma;
+  a.absorb = absorb;
   a.inj = (const double2 *)inj;
   a.psi = (double2 *)psi;
   a.gc = (double2 *)gc;
@@ -241,11 +250,12 @@ ss_status apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q, con
   return obc_run(ctx, a, nb, psi != nullptr, info);
 }
 
-ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q, const ss_c128 *sigma, int m,
-                           const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info) {
+ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q, const ss_c128 *sigma, double absorb,
+                           int m, const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info) {
   ObcArgs a{};
   a.Q = (const double2 *)Q;
   a.sigma = (const double2 *)sigma;
+  a.absorb = absorb;
   a.inj = (const double2 *)inj;
   a.psi = nullptr;
   a.gc = (double2 *)gc;

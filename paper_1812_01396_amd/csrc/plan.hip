@@ -209,10 +209,10 @@ ss_status run_chunk(ss_plan *p, Group &g, const Chunk &c) {
   int *i_sig = g.info, *i_pre = g.info + g.chunk, *i_obc = g.info + 2 * g.chunk, *i_it = g.info + 3 * g.chunk;
   SS_TRY(lead_selfenergy(x, C, s, C, nullptr, nullptr, nullptr, nullptr, nullptr, c.rb.E, p->opts.eta,
                          p->opts.sigma_tol, p->opts.sigma_passes, g.sigma, i_it, nullptr, i_sig, c.lead_tab));
-  SS_TRY(precompute_ragged(x, c.rb, SS_PREC_FP64, g.Q, i_pre));
+  SS_TRY(precompute_ragged(x, c.rb, p->opts.absorb, SS_PREC_FP64, g.Q, i_pre));
   const int mm = c.any_psi ? m : 0;
   if (mm > 0) SS_TRY(injection_left(x, C, s, g.sigma, 0.0, mm, g.inj, nullptr));
-  SS_TRY(apply_obc_ragged(x, c.rb, g.Q, g.sigma, mm, g.inj, mm > 0 ? c.psi_tab : nullptr, g.gc, i_obc));
+  SS_TRY(apply_obc_ragged(x, c.rb, g.Q, g.sigma, p->opts.absorb, mm, g.inj, mm > 0 ? c.psi_tab : nullptr, g.gc, i_obc));
   SS_TRY(transmission(x, C, s, g.gc, g.sigma, g.T));
   hipLaunchKernelGGL(k_plan_scatter, dim3(cdiv(C, 256)), dim3(256), 0, x->stream, (const double *)g.T,
                      (const int *)g.info, (const int *)c.orig, C, g.chunk, p->T, p->info);
@@ -388,7 +388,8 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
   ctx->err.clear();
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "hipSetDevice failed");
   if (n < 1 || !inst || !opts || !T || !info) return fail(ctx, SS_ERR_ARG, "ss_plan_create: null argument or n < 1");
-  if (opts->m < 0 || opts->m > SS_MAX_S || opts->eta < 0 || opts->sigma_tol < 0 || opts->sigma_passes < 0)
+  if (opts->m < 0 || opts->m > SS_MAX_S || opts->eta < 0 || !(opts->absorb >= 0) || !std::isfinite(opts->absorb) ||
+      opts->sigma_tol < 0 || opts->sigma_passes < 0)
     return fail(ctx, SS_ERR_ARG, "ss_plan_create: option out of range");
   for (int i = 0; i < n; ++i) {
     const ss_instance &in = inst[i];

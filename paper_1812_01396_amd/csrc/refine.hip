@@ -9,7 +9,9 @@
 //     backward  g_n = D_n^{-1} r_n,  g_i = D_i^{-1} (r_i - A_{i,i+1} g_{i+1})
 //     forward   y_1 = g_1,           y_i = g_i - X_i y_{i-1}
 // which is exact for the factors it is given: with factors from lower-precision products the loop
-// converges to the FP64 solution at a rate set by their accuracy.
+// converges to the FP64 solution at a rate set by their accuracy.  With an absorbing boundary
+// (absorb > 0, see sweep.hip) the factors are those of A' = A + i*absorb*[boundary blocks] and the
+// correction uses C' = Sigma + i*absorb*I; the residual is always that of T = A - Sigma itself.
 #include <algorithm>
 #include <cmath>
 
@@ -54,6 +56,7 @@ struct RefArgs {
   double *nrm;   // [batch][2]: ||r||^2, ||b||^2
   int *done;     // [batch]
   double tol;
+  double absorb;  // C' = Sigma + i*absorb*I
 };
 
 __device__ __forceinline__ int ref_set(const RefArgs &a, int inst) {
@@ -209,9 +212,16 @@ __global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_cy(RefArgs a)
   LdRow lb{a.g + (long)inst * nb * sm + (half ? (long)(nb - 1) * sm : 0), m};
   mma_loop<T>(la, lb, m0, s, n0, m, 0, s, acc, lds);
   double2 *cy = a.cy + (long)inst * 2 * sm + half * sm;
+  const double2 *yb = a.g + (long)inst * nb * sm + (half ? (long)(nb - 1) * sm : 0);
   acc_foreach<T>(acc, [&](int rl, int cl, double2 v) {
     const int gr = m0 + rl, gc = n0 + cl;
-    if (gr < s && gc < m) cy[(long)gr * m + gc] = v;
+    if (gr < s && gc < m) {
+      if (a.absorb != 0.0) {  // + i*absorb*y
+        const double2 y = yb[(long)gr * m + gc];
+        v = make_double2(v.x - a.absorb * y.y, v.y + a.absorb * y.x);
+      }
+      cy[(long)gr * m + gc] = v;
+    }
   });
 }
 
@@ -269,6 +279,9 @@ ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, 
   if (!ctx->corner_valid || ctx->corner_batch != batch || ctx->corner_s != s)
     return fail(ctx, SS_ERR_ARG, "ss_refine_psi: no corner factorization for this batch (ss_apply_obc must run "
                                  "last on this context)");
+  if (ctx->fact_absorb != ctx->corner_absorb)
+    return fail(ctx, SS_ERR_ARG, "ss_refine_psi: the kept factors and the corner system were formed with different "
+                                 "absorbing shifts");
   if (tol <= 0) tol = 1e-12;
   if (max_iter <= 0) max_iter = 10;
   const long ss2 = (long)s * s, sm = (long)s * m;
@@ -311,6 +324,7 @@ ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, 
   a.done = (int *)((char *)wMisc + (size_t)batch * 16);
   int *dcount = a.done + batch;
   a.tol = tol;
+  a.absorb = ctx->fact_absorb;
 
   // block solves with the kept diagonal factorizations: D_i of block i was factored at step nb-1-i
   LuDesc dd;

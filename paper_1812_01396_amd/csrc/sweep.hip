@@ -1,5 +1,11 @@
 // Step 1 of SplitSolve (Sec. 3B, Alg. 1): first and last block columns Q of A^{-1}, A = E*S - H.
 //
+// Optional absorbing boundary (Sec. 3B: the split T = A - B C of the open system leaves the choice of B
+// and C free): with absorb > 0 the first and last diagonal blocks are formed as E*S - H + i*absorb*I,
+// i.e. the constant part -i*absorb*I of the boundary self-energies is moved from C into A.  Q is then
+// A'^{-1} B for that A', and the post-processing uses C' = Sigma + i*absorb*I.  absorb = 0 is the
+// paper's A = E*S - H.
+//
 // Every instance runs two independent recursions ("directions") in lockstep, as separate systems of
 // one batch:
 //   direction 0 (first column), 0-based block ib = nb-1-t at step t:
@@ -26,6 +32,7 @@ struct SweepArgs {
   const double2 *const *tab;   // or per set {H_diag, H_upper, S_diag, S_upper} pointers (null: strided)
   const int *kidx;
   const double *E;
+  double absorb;     // i*absorb*I added to the first and last diagonal blocks
   int nk, nb, s;
   const int *nbv;    // per-instance block counts (null: every instance has nb blocks)
   const long *boff;  // per-instance first block in the packed per-block stores (null: inst * nb)
@@ -116,11 +123,13 @@ k_form(SweepArgs a, int t) {
   if (tile < ntile) {
     // D tile: D = A_ib,ib - coupling * previous solution
     const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
+    // absorbing shift of the boundary blocks (both of them when nb == 1)
+    const double shift = a.absorb * ((ib == 0 ? 1 : 0) + (ib == nb - 1 ? 1 : 0));
     auto store = [&](int r, int c, double2 v) {
       const int gr = m0 + r, gc = n0 + c;
       if (gr < s && gc < s) {
         const long o = (long)gr * s + gc;
-        const double2 av = make_double2(e * sd[o].x - hd[o].x, e * sd[o].y - hd[o].y);
+        const double2 av = make_double2(e * sd[o].x - hd[o].x, e * sd[o].y - hd[o].y + (gr == gc ? shift : 0.0));
         M[(long)gr * 2 * s + gc] = csub(av, v);
       }
     };
@@ -313,8 +322,8 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
   return check_launch(ctx, "precompute_columns");
 }
 
-ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int prec,
-                             int flags, ss_c128 *Q, int *info) {
+ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                             double absorb, int prec, int flags, ss_c128 *Q, int *info) {
   const int s = hs->s, nb = hs->nb;
   const long ss2 = (long)s * s;
   SweepArgs a{};
@@ -327,6 +336,7 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   a.tab = nullptr;
   a.kidx = kidx;
   a.E = E;
+  a.absorb = absorb;
   a.nk = hs->nk;
   a.nb = nb;
   a.s = s;
@@ -342,15 +352,17 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
     ctx->fact_batch = batch;
     ctx->fact_nb = nb;
     ctx->fact_s = s;
+    ctx->fact_absorb = absorb;
   }
   return SS_OK;
 }
 
-ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, int prec, ss_c128 *Q, int *info) {
+ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, double absorb, int prec, ss_c128 *Q, int *info) {
   SweepArgs a{};
   a.tab = (const double2 *const *)rb.tab;
   a.kidx = nullptr;
   a.E = rb.E;
+  a.absorb = absorb;
   a.nk = rb.batch;
   a.nb = rb.nb_max;
   a.s = rb.s;

@@ -58,7 +58,8 @@ class _Instance(ctypes.Structure):
 
 class _PlanOpts(ctypes.Structure):
     _fields_ = [
-        ("eta", ctypes.c_double), ("sigma_tol", ctypes.c_double), ("sigma_passes", ctypes.c_int),
+        ("eta", ctypes.c_double), ("absorb", ctypes.c_double), ("sigma_tol", ctypes.c_double),
+        ("sigma_passes", ctypes.c_int),
         ("m", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
         ("mem_bytes", ctypes.c_size_t),
     ]
@@ -104,11 +105,11 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_kernel_timer_read.restype = I
     lib.ss_lead_selfenergy.argtypes = [P, I, I, I, P, P, P, P, P, P, D, D, I, P, P, P, P]
     lib.ss_lead_selfenergy.restype = I
-    lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, I, I, P, P]
+    lib.ss_precompute_columns.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, D, I, I, P, P]
     lib.ss_precompute_columns.restype = I
     lib.ss_lu_factor.argtypes = [P, I, I, P, P, P]
     lib.ss_lu_factor.restype = I
-    lib.ss_apply_obc.argtypes = [P, I, I, I, P, P, I, P, P, P, P]
+    lib.ss_apply_obc.argtypes = [P, I, I, I, P, P, D, I, P, P, P, P]
     lib.ss_apply_obc.restype = I
     lib.ss_transmission.argtypes = [P, I, I, P, P, P]
     lib.ss_transmission.restype = I
@@ -290,12 +291,14 @@ def _btd(Hd, Hu, Sd, Su, dev):
 
 
 def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, info=None, validate: bool = True,
-                          prec: int = SS_PREC_FP64, keep_factors: bool = False):
+                          prec: int = SS_PREC_FP64, keep_factors: bool = False, absorb: float = 0.0):
     """Q = first and last block columns of (E S - H)^{-1} for every instance (Sec. 3B, Step 1).
 
     Hd, Sd: [nk, nb, s, s]; Hu, Su: [nk, nb-1, s, s] (or without the leading nk).  E: [batch] float64.
     prec: SS_PREC_FP64 or SS_PREC_FP32 (products of the recursion); keep_factors keeps the first-column
-    recursion's factors in the context for ss_refine_psi.  Returns (Q [batch, nb, s, 2s], info [batch]).
+    recursion's factors in the context for ss_refine_psi; absorb: absorbing boundary (i*absorb*I on the
+    first and last diagonal blocks; pass the same value to ss_apply_obc).  Returns (Q [batch, nb, s, 2s],
+    info [batch]).
     """
     dev = ctx.device
     btd, nk, nb, s = _btd(Hd, Hu, Sd, Su, dev)
@@ -309,8 +312,8 @@ def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, in
     info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
     _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
     flags = SS_KEEP_FACTORS if keep_factors else 0
-    ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), int(prec),
-                                            flags, _ptr(Q), _ptr(info)))
+    ctx.check(ctx.lib.ss_precompute_columns(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), float(absorb),
+                                            int(prec), flags, _ptr(Q), _ptr(info)))
     return Q, info
 
 
@@ -331,10 +334,12 @@ def ss_lu_factor(ctx: Context, A, perm=None, info=None):
     return A, perm, info
 
 
-def ss_apply_obc(ctx: Context, Q, sigma, inj=None, psi=None, gc=None, info=None, want_gc: bool = True):
+def ss_apply_obc(ctx: Context, Q, sigma, inj=None, psi=None, gc=None, info=None, want_gc: bool = True,
+                 absorb: float = 0.0):
     """Steps 2-4 (Sec. 3B, Eq. (x)): psi = Q (b' + z) and the corner of G^R.
 
-    Q: [batch, nb, s, 2s]; sigma: [batch, 2, s, s]; inj = b': [batch, 2s, m] or None.
+    Q: [batch, nb, s, 2s] from ss_precompute_columns with the same absorb; sigma: [batch, 2, s, s];
+    inj = b': [batch, 2s, m] or None.
     Returns (psi [batch, nb, s, m] or None, gc [batch, 2s, 2s] or None, info [batch] int32).
     """
     dev = ctx.device
@@ -351,7 +356,7 @@ def ss_apply_obc(ctx: Context, Q, sigma, inj=None, psi=None, gc=None, info=None,
         gc = gc if gc is not None else torch.empty(batch, 2 * s, 2 * s, dtype=torch.complex128, device=dev)
         _need(gc, torch.complex128, dev, "gc", (batch, 2 * s, 2 * s))
     info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
-    ctx.check(ctx.lib.ss_apply_obc(ctx.handle, batch, nb, s, _ptr(Q), _ptr(sigma), m, _ptr(inj), _ptr(psi),
+    ctx.check(ctx.lib.ss_apply_obc(ctx.handle, batch, nb, s, _ptr(Q), _ptr(sigma), float(absorb), m, _ptr(inj), _ptr(psi),
                                    _ptr(gc) if want_gc else None, _ptr(info)))
     return (psi if m > 0 else None), (gc if want_gc else None), info
 
@@ -438,7 +443,8 @@ class Plan:
     """
 
     def __init__(self, ctx: Context, instances, eta: float, m: int = 0, use_graph: bool = True,
-                 autotune: bool = True, sigma_tol: float = 0.0, sigma_passes: int = 0, mem_bytes: int = 0):
+                 autotune: bool = True, sigma_tol: float = 0.0, sigma_passes: int = 0, mem_bytes: int = 0,
+                 absorb: float = 0.0):
         dev = ctx.device
         n = len(instances)
         if n < 1:
@@ -461,7 +467,7 @@ class Plan:
             arr[i] = _Instance(nb, s, x.E, x.Hd.data_ptr(), x.Hu.data_ptr() if nb > 1 else None, x.Sd.data_ptr(),
                                x.Su.data_ptr() if nb > 1 else None, x.H00.data_ptr(), x.H01.data_ptr(),
                                x.S00.data_ptr(), x.S01.data_ptr(), None if x.psi is None else x.psi.data_ptr())
-        opts = _PlanOpts(float(eta), float(sigma_tol), int(sigma_passes), int(m), int(bool(use_graph)),
+        opts = _PlanOpts(float(eta), float(absorb), float(sigma_tol), int(sigma_passes), int(m), int(bool(use_graph)),
                          int(bool(autotune)), int(mem_bytes))
         self.ctx = ctx
         self.instances = list(instances)

@@ -45,22 +45,32 @@ def _stack_sets(insts):
     return [np.stack([getattr(i, f) for i in insts]) for f in ("Hd", "Hu", "Sd", "Su")]
 
 
-@pytest.mark.parametrize("nb,s", [(1, 5), (2, 16), (5, 40), (3, 72), (4, 130), (2, 33)])
-def test_precompute_columns_vs_oracle(ctx, nb, s):
+def _shifted_blocks(inst, E, absorb):
+    """Blocks of A' = E S - H + i*absorb*I on the first and last diagonal blocks (absorbing boundary)."""
+    ad, au, al = transport.device_blocks(inst.Hd, inst.Hu, inst.Sd, inst.Su, E)
+    ad = ad.copy()
+    eye = np.eye(ad.shape[1])
+    ad[0] = ad[0] + 1j * absorb * eye
+    ad[-1] = ad[-1] + 1j * absorb * eye
+    return ad, au, al
+
+
+@pytest.mark.parametrize("nb,s,absorb", [(1, 5, 0.0), (2, 16, 0.0), (5, 40, 0.0), (3, 72, 0.0), (4, 130, 0.0),
+                                         (2, 33, 0.0), (1, 5, 0.7), (5, 40, 0.7), (4, 130, 1.3)])
+def test_precompute_columns_vs_oracle(ctx, nb, s, absorb):
     import paper_1812_01396_amd as ss
-    print(f"precompute nb={nb} s={s}", flush=True)
+    print(f"precompute nb={nb} s={s} absorb={absorb}", flush=True)
     insts = [synth.random_btd(nb, s, seed=1000 + 7 * nb + s + k) for k in range(2)]
     Es = np.array([0.31, -0.47, 0.05])
     kidx = np.array([0, 1, 1], dtype=np.int32)
     hd, hu, sd, su = _stack_sets(insts)
     q, info = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), _dev(Es, torch.float64),
-                                       kidx=_dev(kidx, torch.int32))
+                                       kidx=_dev(kidx, torch.int32), absorb=absorb)
     torch.cuda.synchronize()
     q = q.cpu().numpy()
     assert (info.cpu().numpy() == 0).all()
     for b, (E, k) in enumerate(zip(Es, kidx)):
-        ad, au, al = transport.device_blocks(insts[k].Hd, insts[k].Hu, insts[k].Sd, insts[k].Su, E)
-        ref = transport.first_last_columns(ad, au, al)
+        ref = transport.first_last_columns(*_shifted_blocks(insts[k], E, absorb))
         assert _rel(q[b], ref) <= TOL, (b, _rel(q[b], ref))
 
 
@@ -130,14 +140,14 @@ def test_selfenergy_vs_oracle(ctx, cell_kind, s):
         assert _rel(sig[b, 1], sr) <= tol, (b, _rel(sig[b, 1], sr), tol)
 
 
-def _pipeline(ctx, inst_sets, Es, kidx, eta, inj):
+def _pipeline(ctx, inst_sets, Es, kidx, eta, inj, absorb=0.0):
     import paper_1812_01396_amd as ss
     hd, hu, sd, su = _stack_sets(inst_sets)
     leads = [np.stack([getattr(i, f) for i in inst_sets]) for f in ("H00", "H01", "S00", "S01")]
     E_d, k_d = _dev(Es, torch.float64), _dev(kidx, torch.int32)
     sig, iters, resid, info_s = ss.ss_lead_selfenergy(ctx, *(_dev(x) for x in leads), E_d, eta, kidx=k_d)
-    q, info_q = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), E_d, kidx=k_d)
-    psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=_dev(inj) if inj is not None else None)
+    q, info_q = ss.ss_precompute_columns(ctx, _dev(hd), _dev(hu), _dev(sd), _dev(su), E_d, kidx=k_d, absorb=absorb)
+    psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=_dev(inj) if inj is not None else None, absorb=absorb)
     T = ss.ss_transmission(ctx, gc, sig)
     torch.cuda.synchronize()
     for i in (info_s, info_q, info_o):
@@ -146,15 +156,18 @@ def _pipeline(ctx, inst_sets, Es, kidx, eta, inj):
                 gc=gc.cpu().numpy(), T=T.cpu().numpy())
 
 
-@pytest.mark.parametrize("nb,s,m", [(1, 6, 2), (4, 40, 3), (3, 72, 5), (2, 100, 1)])
-def test_obc_psi_transmission_vs_oracle(ctx, nb, s, m):
-    print(f"pipeline nb={nb} s={s} m={m}", flush=True)
+@pytest.mark.parametrize("nb,s,m,absorb", [(1, 6, 2, 0.0), (4, 40, 3, 0.0), (3, 72, 5, 0.0), (2, 100, 1, 0.0),
+                                           (1, 6, 2, 1.0), (4, 40, 3, 1.0), (3, 72, 5, 0.5), (2, 100, 1, 2.0)])
+def test_obc_psi_transmission_vs_oracle(ctx, nb, s, m, absorb):
+    """The corner of G^R, psi and T do not depend on the split: the absorbing boundary (absorb > 0) gives
+    the oracle's direct solve of the open system as the paper's split does."""
+    print(f"pipeline nb={nb} s={s} m={m} absorb={absorb}", flush=True)
     insts = [synth.random_btd(nb, s, seed=2000 + s + k) for k in range(2)]
     Es = np.array([0.15, -0.35])
     kidx = np.array([0, 1], dtype=np.int32)
     eta = 1e-8
     inj = np.stack([synth.injection_block(s, m, 50 + b) for b in range(2)])
-    out = _pipeline(ctx, insts, Es, kidx, eta, inj)
+    out = _pipeline(ctx, insts, Es, kidx, eta, inj, absorb)
     for b in range(2):
         inst = insts[kidx[b]]
         ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
@@ -166,21 +179,23 @@ def test_obc_psi_transmission_vs_oracle(ctx, nb, s, m):
             assert abs(out["T"][b, j] - ref[key]) <= tol * max(1.0, abs(ref[key]))
 
 
-def test_chain_crystal_all_energies(ctx):
+@pytest.mark.parametrize("absorb", [0.0, 1.0])
+def test_chain_crystal_all_energies(ctx, absorb):
     """Random 16-orbital chain, 32 blocks, 64 energies in [-3, 3]: T equals the stored channel counts."""
     import os
     rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "chain16_channels.txt"), comments="#")
     cell = synth.chain_cell(16, 0)
     inst = synth.device_from_cell(cell, 32)
     Es = rows[:, 0]
-    out = _pipeline(ctx, [inst], Es, np.zeros(len(Es), np.int32), 1e-8, None)
+    out = _pipeline(ctx, [inst], Es, np.zeros(len(Es), np.int32), 1e-8, None, absorb)
     for b, E in enumerate(Es):
         assert abs(out["T"][b, 0] - rows[b, 1]) <= 1e-8, (E, out["T"][b], rows[b, 1])
         assert abs(out["T"][b, 1] - rows[b, 1]) <= 1e-8
     # and element-wise against the oracle on a sample of energies
     for b in range(0, len(Es), 9):
         ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, *cell, Es[b], 1e-8)
-        assert _rel(out["q"][b], ref["q"]) <= TOL
+        q_ref = transport.first_last_columns(*_shifted_blocks(inst, Es[b], absorb)) if absorb else ref["q"]
+        assert _rel(out["q"][b], q_ref) <= TOL
         assert abs(out["T"][b, 0] - ref["t_lr"]) <= TOL * max(1.0, ref["t_lr"])
 
 

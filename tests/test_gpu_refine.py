@@ -33,18 +33,19 @@ def ctx():
     c.close()
 
 
-def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True):
+def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True, absorb=0.0):
     import paper_1812_01396_amd as ss
     hd, hu, sd, su = (_dev(np.stack([getattr(i, f) for i in insts])) for f in ("Hd", "Hu", "Sd", "Su"))
     leads = [_dev(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01")]
     E_d, k_d = _dev(Es, torch.float64), _dev(kidx, torch.int32)
     sig, _, _, info_s = ss.ss_lead_selfenergy(ctx, *leads, E_d, eta, kidx=k_d)
-    q, info_q = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E_d, kidx=k_d, prec=prec, keep_factors=True)
+    q, info_q = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E_d, kidx=k_d, prec=prec, keep_factors=True,
+                                         absorb=absorb)
     if inj is None:
         inj_d, rank = ss.ss_injection_left(ctx, sig, mmax)
     else:
         inj_d, rank = _dev(inj), None
-    psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=inj_d)
+    psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=inj_d, absorb=absorb)
     psi0 = psi.clone()
     out = dict(sig=sig, q=q, gc=gc, psi0=psi0, inj=inj_d, rank=rank)
     if refine:
@@ -73,15 +74,17 @@ def test_injection_factor_reproduces_gamma(ctx):
         assert 1 <= out["rank"][b] <= 24
 
 
-@pytest.mark.parametrize("prec", [0, 1])
-def test_refined_psi_matches_oracle(ctx, prec):
+@pytest.mark.parametrize("prec,absorb", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0)])
+def test_refined_psi_matches_oracle(ctx, prec, absorb):
+    """Refinement of psi on the open system from the kept factors, for the paper's split and for the
+    absorbing one (the factors of A' and C' = Sigma + i*absorb*I)."""
     nb, s, m = 4, 40, 3
     insts = [synth.random_btd(nb, s, seed=700 + k) for k in range(2)]
     Es = np.array([0.21, -0.33])
     kidx = np.array([0, 1], np.int32)
     eta = 1e-8
     inj = np.stack([synth.injection_block(s, m, 90 + b) for b in range(2)])
-    out = _run(ctx, insts, Es, kidx, eta, prec, inj=inj)
+    out = _run(ctx, insts, Es, kidx, eta, prec, inj=inj, absorb=absorb)
     for b in range(2):
         inst = insts[kidx[b]]
         ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
@@ -117,3 +120,20 @@ def test_crystal_near_closed_device_eigenvalue(ctx):
     Es = rows[:, 0]
     out = _run(ctx, [inst], Es, np.zeros(len(Es), np.int32), 1e-8, 1, mmax=16)
     assert np.abs(out["T_psi"] - rows[:, 1]).max() <= 1e-8
+
+
+def test_refine_rejects_mismatched_absorbing_shift(ctx):
+    """Kept factors of A' (absorb = 1) and a corner system formed with C' for absorb = 0 do not describe one
+    split: the refinement refuses them (host-side argument check, nothing is launched)."""
+    import paper_1812_01396_amd as ss
+    inst = synth.random_btd(3, 8, seed=31)
+    hd, hu, sd, su = (_dev(getattr(inst, f)[None]) for f in ("Hd", "Hu", "Sd", "Su"))
+    leads = [_dev(getattr(inst, f)[None]) for f in ("H00", "H01", "S00", "S01")]
+    E_d = _dev(np.array([0.2]), torch.float64)
+    sig, _, _, _ = ss.ss_lead_selfenergy(ctx, *leads, E_d, 1e-8)
+    q, _ = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E_d, keep_factors=True, absorb=1.0)
+    inj = _dev(synth.injection_block(8, 2, 3)[None])
+    psi, _, _ = ss.ss_apply_obc(ctx, q, sig, inj=inj, absorb=0.0)
+    with pytest.raises(ss.splitsolve.SplitSolveError):
+        ss.ss_refine_psi(ctx, hd, hu, sd, su, E_d, q, sig, inj, psi)
+    torch.cuda.synchronize()

@@ -187,6 +187,58 @@ def test_smw_identities():
     assert np.linalg.norm(psi - out["psi"]) <= 1e-10 * np.linalg.norm(out["psi"])
 
 
+def _absorbing_split(inst, E, sigma_l, sigma_r, inj, absorb):
+    """The split T = A' - B C' of Sec. 3B with the constant part -i*absorb*I of both self-energies moved
+    into A: A' = A + i*absorb*I on the first and last diagonal blocks, C' = Sigma + i*absorb*I.
+    Returns (corner Q' R'^{-1}, psi Q' (b' + z'))."""
+    ad, au, al = transport.device_blocks(inst.Hd, inst.Hu, inst.Sd, inst.Su, E)
+    eye = np.eye(ad.shape[1])
+    ad2 = ad.copy()
+    ad2[0] = ad2[0] + 1j * absorb * eye
+    ad2[-1] = ad2[-1] + 1j * absorb * eye
+    q = transport.first_last_columns(ad2, au, al)
+    r, z = transport.smw_terms(q, sigma_l + 1j * absorb * eye, sigma_r + 1j * absorb * eye, inj)
+    gc = np.vstack([q[0], q[-1]]) @ np.linalg.inv(r)
+    return gc, np.einsum("nij,jm->nim", q, inj + z)
+
+
+@pytest.mark.parametrize("absorb", [0.3, 1.0, 4.0])
+@pytest.mark.parametrize("nb", [1, 2, 6])
+def test_smw_with_absorbing_boundary(absorb, nb):
+    """Sec. 3B leaves B and C free: moving -i*absorb*I of the self-energies from C into A (A' - B C' = T)
+    gives the same corner of T^{-1} and the same psi, for any absorb and also for a single block (where
+    both shifts land on the one diagonal block)."""
+    inst = synth.random_btd(nb, 5, seed=44 + nb)
+    E, eta = 0.25, 1e-8
+    inj = synth.injection_block(5, 3, 10)
+    out = _solve(inst, E, eta, inj=inj)
+    gc, psi = _absorbing_split(inst, E, out["sigma_l"], out["sigma_r"], inj, absorb)
+    assert np.linalg.norm(gc - out["gc"]) <= 1e-10 * np.linalg.norm(out["gc"])
+    assert np.linalg.norm(psi - out["psi"]) <= 1e-10 * np.linalg.norm(out["psi"])
+
+
+@pytest.mark.parametrize("which", [100, 260, 400])
+def test_absorbing_boundary_next_to_closed_device_eigenvalue(which):
+    """At E within 1e-11 of an eigenvalue of the closed device (E S - H singular) the correction of the
+    closed split loses digits in proportion to the conditioning of A (here 1e-5 and worse in T, the
+    instance itself being well posed), while the absorbing split, whose A' has no real eigenvalues,
+    stays at rounding level.  Crystal of the 16-orbital chain cell, 32 blocks: T is an integer."""
+    cell = synth.chain_cell(16, 0)
+    inst = synth.device_from_cell(cell, 32)
+    h = linalg.assemble_dense(inst.Hd, inst.Hu, np.conj(np.transpose(inst.Hu, (0, 2, 1))))
+    E = float(np.linalg.eigvalsh(h)[which]) + 1e-11
+    ref = _solve(inst, E)
+    zero = np.zeros((32, 1), dtype=np.complex128)
+    errs = {}
+    for absorb in (0.0, 1.0):
+        gc, _ = _absorbing_split(inst, E, ref["sigma_l"], ref["sigma_r"], zero, absorb)
+        t_lr, t_rl = transport.caroli(gc, ref["sigma_l"], ref["sigma_r"])
+        errs[absorb] = max(abs(t_lr - ref["t_lr"]), abs(t_rl - ref["t_rl"]))
+    assert abs(ref["t_lr"] - round(ref["t_lr"])) <= 1e-6  # O(eta) from the integer channel count
+    assert errs[1.0] <= 1e-12
+    assert errs[0.0] >= 1e-7  # the closed split really is ill-conditioned here
+
+
 def test_alg1_reading_reproduces_first_and_last_columns():
     """Readings of Alg. 1 (Sec. 3B): X_{n_B+1} = 0, A_{1,0} := 1 and Q_0 = -1 give the first block column;
     the mirrored recursion with A_{n_B,n_B+1} := 1 gives the last one."""
@@ -371,3 +423,22 @@ def test_lu_partial_pivot_tie_rule_and_zero_pivot():
     assert info == 2 and perm[0] == 1
     L = np.tril(lu, -1) + np.eye(3)
     assert np.allclose(b[perm], L @ np.triu(lu))
+
+
+def test_golden_dft512_is_consistent():
+    """The stored oracle transmissions of the s = 512 crystal (256 instances): T_LR = T_RL (an identity),
+    T = the band-structure channel count up to O(eta) terms, and the block-Thomas values equal a dense LU
+    solve of the assembled 20480 x 20480 open system on the two instances farthest from the integer."""
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden")
+    ref = np.loadtxt(os.path.join(here, "dft512_transmission.txt"), comments="#")
+    assert ref.shape == (256, 8)
+    assert np.abs(ref[:, 3] - ref[:, 4]).max() <= 1e-10
+    assert np.abs(ref[:, 3] - ref[:, 6]).max() <= 1e-6
+    assert (ref[:, 5] >= 20).all() and (ref[:, 5] <= 40).all()   # decimation passes at eta = 1e-8
+    dense = np.loadtxt(os.path.join(here, "dft512_dense_check.txt"), comments="#")
+    assert dense.shape[0] == 2
+    for row in dense:
+        b = int(row[0])
+        assert np.allclose(row[3:5], ref[b, 3:5], rtol=0, atol=1e-14)
+        assert np.abs(row[1:3] - row[3:5]).max() <= 1e-10
