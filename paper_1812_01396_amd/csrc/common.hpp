@@ -54,6 +54,10 @@ __device__ __forceinline__ double dpp_double(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// Maximum that propagates NaN (fmax drops a NaN operand, which would let a NaN iterate pass a
+// convergence test): NaN if either operand is NaN.
+__device__ __forceinline__ double nanmax(double a, double b) { return (a != a) ? a : ((b > a || b != b) ? b : a); }
+
 // LAPACK's pivot magnitude |Re| + |Im|
 __device__ __forceinline__ double cabs1(double2 a) { return fabs(a.x) + fabs(a.y); }
 

@@ -58,7 +58,10 @@ __device__ __forceinline__ double2 *dec_mat(const DecArgs &a, int inst, int whic
   return a.st + ((long)inst * 7 + which) * a.s * a.s;
 }
 
+// Maximum of non-negative doubles through their bit patterns (monotone for v >= 0); a NaN is stored as
+// the positive quiet NaN, whose pattern lies above every finite value and +Inf, so it survives.
 __device__ __forceinline__ void atomic_max_pos(unsigned long long *p, double v) {
+  if (v != v) v = __longlong_as_double(0x7ff8000000000000LL);
   atomicMax(p, (unsigned long long)__double_as_longlong(v));
 }
 
@@ -87,9 +90,9 @@ __global__ void k_dec_init(DecArgs a) {
     M[(long)r * 3 * s + c] = a0;
     M[(long)r * 3 * s + s + c] = am1;
     M[(long)r * 3 * s + 2 * s + c] = a1;
-    lmax = fmax(lmax, hypot(a0.x, a0.y));
+    lmax = nanmax(lmax, hypot(a0.x, a0.y));
   }
-  for (int off = 32; off >= 1; off >>= 1) lmax = fmax(lmax, __shfl_xor(lmax, off));
+  for (int off = 32; off >= 1; off >>= 1) lmax = nanmax(lmax, __shfl_xor(lmax, off));
   if ((threadIdx.x & 63) == 0) atomic_max_pos((unsigned long long *)(a.scale + inst), lmax);
 }
 
@@ -163,7 +166,7 @@ __global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_update(DecArg
       const double2 nv = cneg(v);
       alpha_n[(long)gr * s + gc] = nv;
       M[(long)gr * 3 * s + 2 * s + gc] = nv;
-      amax = fmax(amax, hypot(nv.x, nv.y));
+      amax = nanmax(amax, hypot(nv.x, nv.y));
     }
   });
   // beta <- -beta G beta
@@ -176,12 +179,12 @@ __global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_update(DecArg
       const double2 nv = cneg(v);
       beta_n[(long)gr * s + gc] = nv;
       M[(long)gr * 3 * s + s + gc] = nv;
-      bmax = fmax(bmax, hypot(nv.x, nv.y));
+      bmax = nanmax(bmax, hypot(nv.x, nv.y));
     }
   });
   for (int off = 32; off >= 1; off >>= 1) {
-    amax = fmax(amax, __shfl_xor(amax, off));
-    bmax = fmax(bmax, __shfl_xor(bmax, off));
+    amax = nanmax(amax, __shfl_xor(amax, off));
+    bmax = nanmax(bmax, __shfl_xor(bmax, off));
   }
   if ((threadIdx.x & 63) == 0) {
     atomic_max_pos(a.nrm + 2 * inst, amax);

@@ -71,6 +71,25 @@ def test_adam_first_step_closed_form():
     assert state["t"] == 1
 
 
+def test_adam_second_step_worked_example():
+    """Two steps on one scalar with gradients +1 then -1, beta1 = 0.9, beta2 = 0.999 (Kingma & Ba).
+    Worked by hand: after step 2 the first moment is 0.9*0.1 - 0.1 = -0.01 and its bias correction
+    1 - 0.81 = 0.19, so m_hat = -1/19; the second moment is 0.999*0.001 + 0.001 = 0.001999 with
+    correction 1 - 0.998001 = 0.001999, so v_hat = 1 exactly.  Step 1 moves by -lr/(1 + eps), step 2 by
+    +lr/19/(1 + eps).  A beta1/beta2 slip in either moment, or a bias correction taken at t = 1 again,
+    changes the second move."""
+    lr, eps = 0.01, 1e-8
+    params = [(np.array([[0.0]]), np.array([0.0]))]
+    state = {}
+    p1 = warmstart.adam_step(params, [(np.array([[1.0]]), np.array([1.0]))], state, lr, eps=eps)
+    p2 = warmstart.adam_step(p1, [(np.array([[-1.0]]), np.array([-1.0]))], state, lr, eps=eps)
+    first = -lr / (1.0 + eps)
+    assert abs(p1[0][0][0, 0] - first) <= 1e-17
+    assert abs(p2[0][0][0, 0] - (first + lr / 19.0 / (1.0 + eps))) <= 1e-17
+    assert abs(p2[0][1][0] - p2[0][0][0, 0]) == 0.0
+    assert state["t"] == 2
+
+
 def _contracting_pair(s, seed):
     rng = np.random.default_rng(seed)
     M = rng.standard_normal((s, s)) + 1j * rng.standard_normal((s, s))
