@@ -211,6 +211,19 @@ ss_status ss_apply_obc(ss_ctx *ctx, int batch, int nb, int s, const ss_c128 *Q,
 ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
                           double *T);
 
+/* ss_transmission for callers that cannot allocate device memory (code under stream or graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the same kernels and the same result, but the
+ * per-tile partial sums live in a fixed device array of SS_TRANS_SCRATCH_DOUBLES doubles (8 MiB per GPU,
+ * held from library load until the process ends) instead of the context's workspace.  The call
+ * allocates nothing and never waits for the stream.  It accepts batch * 2 * ceil(s/32)^2 <=
+ * SS_TRANS_SCRATCH_DOUBLES (s = 1024: batch <= 512; s = 512: batch <= 2048) and returns SS_ERR_ARG
+ * beyond that.  Every call on one GPU shares that GPU's array and overwrites it (nothing in it needs to
+ * start cleared): calls that may overlap on one GPU (other streams, other contexts, other host threads)
+ * race and must be ordered by the caller.  Its kernels are not bracketed by ss_kernel_timer. */
+#define SS_TRANS_SCRATCH_DOUBLES (1 << 20)
+ss_status ss_transmission_noalloc(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
+                                  double *T);
+
 /* Injection from the left lead (Sec. 3A: Inj is built from the lead's modes; here from its
  * broadening).  For each instance, a pivoted Cholesky factorization Gamma_L ~ W_L W_L^H of
  * Gamma_L = i (Sigma_L - Sigma_L^H) stops when the largest remaining diagonal entry falls to

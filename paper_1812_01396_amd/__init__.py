@@ -26,5 +26,6 @@ from .splitsolve import (  # noqa: F401
     ss_lu_factor,
     ss_refine_psi,
     ss_transmission,
+    ss_transmission_noalloc,
     ss_transmission_psi,
 )

@@ -117,6 +117,14 @@ ss_status ss_create(ss_ctx **out, int device, void *hip_stream) {
   *out = nullptr;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return SS_ERR_ARG;
+  // the fixed scratch of ss_transmission_noalloc: its device address, once per device, with that device
+  // current (the caller's current device is restored)
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return SS_ERR_DEVICE;
+  if (hipSetDevice(device) != hipSuccess) return SS_ERR_DEVICE;
+  const ss_status sst = transmission_scratch_init(device);
+  (void)hipSetDevice(prev);
+  if (sst != SS_OK) return sst;
   ss_ctx *ctx = new (std::nothrow) ss_ctx();
   if (!ctx) return SS_ERR_NOMEM;
   ctx->device = device;
@@ -278,6 +286,16 @@ ss_status ss_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, cons
   if (batch == 0) return SS_OK;
   if (!gc || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission: null pointer");
   return transmission(ctx, batch, s, gc, sigma, T);
+}
+
+ss_status ss_transmission_noalloc(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
+                                  double *T) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || s < 1) return fail(ctx, SS_ERR_ARG, "ss_transmission_noalloc: size out of range");
+  if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_transmission_noalloc: s > SS_MAX_S");
+  if (batch == 0) return SS_OK;
+  if (!gc || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission_noalloc: null pointer");
+  return transmission_noalloc(ctx, batch, s, gc, sigma, T);
 }
 
 ss_status ss_injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, double tol, int mmax,

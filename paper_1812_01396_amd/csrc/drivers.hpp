@@ -38,6 +38,11 @@ ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q,
                            int m, const ss_c128 *inj, ss_c128 *const *psi_tab, ss_c128 *gc, int *info);
 
 ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T);
+// The same with the partial sums in the library's fixed per-device scratch (no allocation); the scratch
+// address of `device` (current) is looked up by transmission_scratch_init, called from ss_create.
+ss_status transmission_noalloc(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T);
+ss_status transmission_scratch_init(int device);
+size_t transmission_partials(int batch, int s);
 
 ss_status injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, double tol, int mmax, ss_c128 *inj,
                          int *rank);

@@ -12,6 +12,9 @@
 //     T_LR = Re Tr[Gamma_L G_1n Gamma_R G_1n^H] = Re sum_ij (Gamma_L G_1n)_ij conj((G_1n Gamma_R)_ij)
 // (Gamma Hermitian), and likewise T_RL with G_n1 and the leads exchanged.
 #include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <string>
 
 #include "drivers.hpp"
 #include "lu.hpp"
@@ -324,19 +327,74 @@ __global__ void k_trans_sum(const double *partial, int ntile, double *T, int n) 
   T[i] = t;
 }
 
-ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
+// Per-tile partial sums of one transmission call: batch * 2 * (tiles per direction) doubles.
+size_t transmission_partials(int batch, int s) {
+  const size_t tiles = (size_t)cdiv(s, TrTile::BM);
+  return (size_t)batch * 2 * tiles * tiles;
+}
+
+// Both kernels of a transmission call; `partial` holds transmission_partials(batch, s) doubles.  Every
+// partial is written by k_trans before k_trans_sum reads it (same stream), so nothing needs clearing.
+static void launch_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T,
+                                double *partial) {
   const int tiles = cdiv(s, TrTile::BM);
   const int ntile = tiles * tiles;
+  hipLaunchKernelGGL(k_trans, dim3(ntile, 2, batch), dim3(TrTile::NT), 0, ctx->stream, (const double2 *)gc,
+                     (const double2 *)sigma, s, partial);
+  hipLaunchKernelGGL(k_trans_sum, dim3(cdiv(2 * batch, 256)), dim3(256), 0, ctx->stream, (const double *)partial,
+                     ntile, T, 2 * batch);
+}
+
+ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
   void *wP;
-  SS_TRY(workspace(ctx, kSlotMisc, sizeof(double) * (size_t)batch * 2 * ntile, &wP));
+  SS_TRY(workspace(ctx, kSlotMisc, sizeof(double) * transmission_partials(batch, s), &wP));
   {
     KernelScope ks_(ctx, "trans");
-    hipLaunchKernelGGL(k_trans, dim3(ntile, 2, batch), dim3(TrTile::NT), 0, ctx->stream, (const double2 *)gc,
-                       (const double2 *)sigma, s, (double *)wP);
+    launch_transmission(ctx, batch, s, gc, sigma, T, (double *)wP);
   }
-  hipLaunchKernelGGL(k_trans_sum, dim3(cdiv(2 * batch, 256)), dim3(256), 0, ctx->stream, (const double *)wP, ntile,
-                     T, 2 * batch);
   return check_launch(ctx, "transmission");
+}
+
+// ------------------------------------------------------------------ transmission without allocation
+//
+// The partial sums live in a fixed device array instead of the context's workspace.  Host code never
+// uses the array's name as an address (it stands for a host-side shadow there): its device address is
+// looked up once per device with hipGetSymbolAddress and kept in g_trans_scratch.  Every call on one
+// device shares that device's copy; calls that overlap on one device race.
+
+static __device__ __align__(256) double scratch[SS_TRANS_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_trans_scratch_mu;
+std::atomic<double *> g_trans_scratch[kScratchDevices];
+}  // namespace
+
+ss_status transmission_scratch_init(int device) {
+  if (device < 0 || device >= kScratchDevices) return SS_ERR_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_trans_scratch_mu);
+  if (g_trans_scratch[device].load()) return SS_OK;
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != device) return SS_ERR_DEVICE;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return SS_ERR_DEVICE;
+  }
+  g_trans_scratch[device].store((double *)p);
+  return SS_OK;
+}
+
+ss_status transmission_noalloc(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {
+  if (transmission_partials(batch, s) > (size_t)SS_TRANS_SCRATCH_DOUBLES)
+    return fail(ctx, SS_ERR_ARG,
+                "ss_transmission_noalloc: batch * 2 * ceil(s/32)^2 = " + std::to_string(transmission_partials(batch, s)) +
+                    " partial sums exceed the fixed scratch of " + std::to_string(SS_TRANS_SCRATCH_DOUBLES));
+  double *partial = (ctx->device >= 0 && ctx->device < kScratchDevices) ? g_trans_scratch[ctx->device].load() : nullptr;
+  if (!partial) return fail(ctx, SS_ERR_DEVICE, "ss_transmission_noalloc: scratch address of this device unknown");
+  launch_transmission(ctx, batch, s, gc, sigma, T, partial);
+  return check_launch(ctx, "transmission_noalloc");
 }
 
 }  // namespace ss

@@ -24,7 +24,8 @@ SS_KEEP_FACTORS = 1
 EXPORTS = (
     "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_set_lu_width", "ss_synchronize", "ss_status_string", "ss_last_error",
     "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
-    "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_injection_left", "ss_refine_psi",
+    "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_transmission_noalloc",
+    "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
@@ -113,6 +114,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_apply_obc.restype = I
     lib.ss_transmission.argtypes = [P, I, I, P, P, P]
     lib.ss_transmission.restype = I
+    lib.ss_transmission_noalloc.argtypes = [P, I, I, P, P, P]
+    lib.ss_transmission_noalloc.restype = I
     lib.ss_injection_left.argtypes = [P, I, I, P, D, I, P, P]
     lib.ss_injection_left.restype = I
     lib.ss_refine_psi.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, P, P, I, P, P, D, I, P, P]
@@ -371,6 +374,19 @@ def ss_transmission(ctx: Context, gc, sigma, T=None):
     T = T if T is not None else torch.empty(batch, 2, dtype=torch.float64, device=dev)
     _need(T, torch.float64, dev, "T", (batch, 2))
     ctx.check(ctx.lib.ss_transmission(ctx.handle, batch, s, _ptr(gc), _ptr(sigma), _ptr(T)))
+    return T
+
+
+def ss_transmission_noalloc(ctx: Context, gc, sigma, T):
+    """ss_transmission through the library's fixed per-device scratch (no device allocation by the
+    library; T [batch, 2] float64 must be given).  Returns T."""
+    dev = ctx.device
+    batch, n2, _ = gc.shape
+    s = n2 // 2
+    _need(gc, torch.complex128, dev, "gc", (batch, 2 * s, 2 * s))
+    _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    _need(T, torch.float64, dev, "T", (batch, 2))
+    ctx.check(ctx.lib.ss_transmission_noalloc(ctx.handle, batch, s, _ptr(gc), _ptr(sigma), _ptr(T)))
     return T
 
 
