@@ -195,6 +195,51 @@ def golden_errors(workload: str, T_gpu):
                 over_1e_8=int((err.max(axis=1) > 1e-8).sum()), over_1e_10=int((err.max(axis=1) > 1e-10).sum()))
 
 
+def summarize_trace(path: str, steps: int = 1, top: int = 25) -> str:
+    """Per-kernel summary of a rocprofv3 kernel trace: the SQLite database that rocprofv3 writes by default
+    (`*_results.db`, read through its `kernels` view) or a `*kernel_trace.csv`.  Kernels are grouped by
+    name with template arguments kept; per group: launches, total and average duration, share of the
+    summed kernel time; then the busy time (union of all kernel intervals) against the summed time, which
+    shows how much kernels overlap.  `steps` divides the totals (launches and ms per step)."""
+    import csv
+    import sqlite3
+
+    rows = []  # (name, start_ns, end_ns)
+    if path.endswith(".db"):
+        con = sqlite3.connect(path)
+        for name, st, en in con.execute("select name, start, end from kernels"):
+            rows.append((name, int(st), int(en)))
+        con.close()
+    else:
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                rows.append((r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    if not rows:
+        return "no kernels in " + path
+    agg = {}
+    for name, st, en in rows:
+        n, t = agg.get(name, (0, 0))
+        agg[name] = (n + 1, t + (en - st))
+    total = sum(t for _, t in agg.values())
+    iv = sorted((st, en) for _, st, en in rows)
+    busy, cur_s, cur_e = 0, iv[0][0], iv[0][1]
+    for st, en in iv[1:]:
+        if st > cur_e:
+            busy += cur_e - cur_s
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+    busy += cur_e - cur_s
+    span = iv[-1][1] - iv[0][0]
+    lines = [f"# kernel summary of {os.path.basename(path)}: {len(rows)} launches, {steps} step(s)",
+             f"# summed kernel time {total / 1e6 / steps:.1f} ms per step; busy (any kernel running) "
+             f"{busy / 1e6 / steps:.1f} ms per step; first start to last end {span / 1e6:.1f} ms",
+             f"{'share':>6} {'ms/step':>9} {'launches/step':>13} {'avg_us':>9}  kernel"]
+    for name, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
+        lines.append(f"{100.0 * t / total:5.1f}% {t / 1e6 / steps:9.2f} {n / steps:13.1f} {t / n / 1e3:9.1f}  {name}")
+    return "\n".join(lines)
+
+
 def uneven_specs(n: int = UNEVEN["n"], seed: int = UNEVEN["seed"]):
     """(s, nb, E, k, cell_seed) of every instance of the uneven batch; instance i from default_rng([seed, i])."""
     u = UNEVEN
@@ -507,8 +552,7 @@ class Pipeline:
         self.absorb = w["absorb"]
         self.w, self.insts, self.E_np, self.kidx_np, self.inj_np = w, insts, E_np, kidx_np, inj_np
         s, nb, m = w["s"], w["nb"], w["m"]
-        # mixed mode also keeps the factorizations: half the default chunk keeps the footprint in HBM
-        self.chunk = chunk or (w["chunk"] if mode == "fp64" else max(1, w["chunk"] // 2))
+        self.chunk = chunk or w["chunk"]
         self.n = nb_inst = len(E_np)
         dev = self.dev = torch.device("cuda", 0)
 
@@ -535,6 +579,8 @@ class Pipeline:
         self.info_q = torch.empty(nb_inst, dtype=torch.int32, device=dev)
         self.info_o = torch.empty(nb_inst, dtype=torch.int32, device=dev)
         self.T_psi = torch.empty(nb_inst, dtype=torch.float64, device=dev)
+        # mixed: last block row of the unrefined psi (with gc it carries the part of Gamma_L outside W_L)
+        self.psi0 = torch.empty(nb_inst, s, m, dtype=c128, device=dev) if mode == "mixed" else None
         self.rank = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
         self.ir_iters = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
         self.ir_resid = torch.zeros(nb_inst, dtype=torch.float64, device=dev)
@@ -590,12 +636,15 @@ class Pipeline:
             ss.ss_apply_obc(self.ctx, q, sig, inj=self.inj[c0:c1], psi=self.psi[c0:c1], gc=self.gc[c0:c1],
                             info=self.info_o[c0:c1], absorb=self.absorb)
             if mixed:
+                self.psi0[c0:c1].copy_(self.psi[c0:c1, -1])
                 ss.ss_refine_psi(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1], q, sig,
                                  self.inj[c0:c1], self.psi[c0:c1], kidx=self.kidx[c0:c1], tol=self.refine_tol,
                                  iters=self.ir_iters[c0:c1], resid=self.ir_resid[c0:c1])
                 self._fp64_fallback(c0, c1)
-                ss.ss_transmission_psi(self.ctx, self.psi[c0:c1], sig, T=self.T_psi[c0:c1])
-            ss.ss_transmission(self.ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
+                ss.ss_transmission_psi(self.ctx, self.psi[c0:c1], sig, T=self.T_psi[c0:c1], psi0=self.psi0[c0:c1],
+                                       gc=self.gc[c0:c1])
+            else:
+                ss.ss_transmission(self.ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
 
     def recursion_alone(self):
         """Step 1 by itself (no self-energies beside it): wall time (ms) of ss_precompute_columns over
@@ -635,6 +684,7 @@ class Pipeline:
                                  validate=False, prec=ss.SS_PREC_FP64, keep_factors=True, absorb=self.absorb)
         self.info_q[idx] = info_b
         psi_b, gc_b, info_ob = ss.ss_apply_obc(self.ctx, q, sig_b, inj=inj_b, absorb=self.absorb)
+        self.psi0[idx] = psi_b[:, -1]
         it_b = torch.zeros(nbad, dtype=torch.int32, device=self.dev)
         res_b = torch.zeros(nbad, dtype=torch.float64, device=self.dev)
         ss.ss_refine_psi(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, E_b, q, sig_b, inj_b, psi_b, kidx=k_b,
@@ -670,9 +720,16 @@ def main():
                     help="only measure this GPU's FP64/FP32 matrix-core, FP64 vector and copy rates")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the extra untimed passes that time the recursion (for profiler runs)")
+    ap.add_argument("--summarize-trace", default=None, metavar="PATH",
+                    help="only print a per-kernel summary of a rocprofv3 kernel trace (*_results.db or "
+                         "*kernel_trace.csv) and exit (no GPU needed)")
+    ap.add_argument("--trace-steps", type=int, default=1, help="--summarize-trace: steps the trace covers")
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
+    if args.summarize_trace:
+        print(summarize_trace(args.summarize_trace, args.trace_steps))
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: run with --gpus 1 (the library has no multi-GPU path)",
@@ -802,6 +859,7 @@ def main():
         "t_err_vs_oracle": t_err,
         # |T - T_oracle| / max(1, T_oracle) over every instance against the stored oracle values
         "t_err_all": golden_errors(args.workload, T_np),
+        "device_mem_used_gib": round((torch.cuda.mem_get_info()[1] - torch.cuda.mem_get_info()[0]) / 2**30, 1),
     }
     print(json.dumps(out))
 

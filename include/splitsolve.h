@@ -141,10 +141,12 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
                              const int *kidx, const double *E, double eta, double tol,
                              int max_iter, ss_c128 *sigma, int *iters, double *resid, int *info);
 
-/* Precision of the recursion's block products in ss_precompute_columns.  The LU factorizations, the
- * triangular solves, the corner system and every residual are always FP64. */
+/* Precision of the recursion's block products in ss_precompute_columns.  Storage is always FP64; the
+ * LU panels (pivot search and elimination inside a panel), the triangular leaves, the corner system
+ * and every residual are always FP64. */
 #define SS_PREC_FP64 0 /* complex FP64 products (FP64 matrix cores)                           */
-#define SS_PREC_FP32 1 /* complex FP32 products with FP32 accumulation, FP64 storage            */
+#define SS_PREC_FP32 1 /* complex FP32 products with FP32 accumulation: the block formations,   */
+                       /* the chain, and the LU's trailing and triangular-solve updates          */
 
 /* flags of ss_precompute_columns */
 #define SS_KEEP_FACTORS 1 /* keep the first-column recursion's factors in the context for     */
@@ -249,9 +251,18 @@ ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kid
                         ss_c128 *psi, double tol, int max_iter, int *iters, double *resid);
 
 /* Transmission carried by a wave function injected from the left lead with b' = [W_L; 0]:
- * T [batch] = Re Tr[psi_nb^H Gamma_R psi_nb] (psi [batch][nb][s][m], sigma [batch][2][s][s]). */
+ * T [batch] = Re Tr[psi_nb^H Gamma_R psi_nb] (psi [batch][nb][s][m], sigma [batch][2][s][s]).
+ *
+ * The injection factor keeps at most m columns of Gamma_L, whose tail (the broadening that eta gives
+ * the closed channels, O(eta) per mode, hundreds of modes) then misses from this T.  With psi0 and gc
+ * (both, or both NULL) the tail is added back through the corner of G^R:
+ *     T = Re Tr[psi_nb^H Gamma_R psi_nb] + (T_RL(gc) - Re Tr[psi0^H Gamma_R psi0]),
+ * where gc [batch][2s][2s] is the corner that ss_apply_obc returned together with the unrefined psi and
+ * psi0 [batch][s][m] is that psi's last block row.  Since psi0 = G_n1 W_L for the same G_n1 as gc, the
+ * bracket is Re Tr[Gamma_R G_n1 (Gamma_L - W_L W_L^H) G_n1^H]: a term as small as the tail, so the
+ * error of a low-precision gc enters T only in proportion to it. */
 ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi,
-                              const ss_c128 *sigma, double *T);
+                              const ss_c128 *sigma, const ss_c128 *psi0, const ss_c128 *gc, double *T);
 
 /* ---------------------------------------------------------------- learned warm start
  * The decimation takes no starting iterate; Newton's method on the fixed-point equation of the

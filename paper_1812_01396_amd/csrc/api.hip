@@ -323,13 +323,15 @@ ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kid
 }
 
 ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
-                              double *T) {
+                              const ss_c128 *psi0, const ss_c128 *gc, double *T) {
   SS_TRY(enter(ctx));
   if (batch < 0 || nb < 1 || s < 1 || m < 1) return fail(ctx, SS_ERR_ARG, "ss_transmission_psi: size out of range");
   if (s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_transmission_psi: s > SS_MAX_S");
   if (batch == 0) return SS_OK;
   if (!psi || !sigma || !T) return fail(ctx, SS_ERR_ARG, "ss_transmission_psi: null pointer");
-  return transmission_psi(ctx, batch, nb, s, m, psi, sigma, T);
+  if ((psi0 == nullptr) != (gc == nullptr))
+    return fail(ctx, SS_ERR_ARG, "ss_transmission_psi: psi0 and gc are given together or not at all");
+  return transmission_psi(ctx, batch, nb, s, m, psi, sigma, psi0, gc, T);
 }
 
 // ---------------------------------------------------------------- learned warm start

@@ -71,7 +71,12 @@ ss_status sigma_encode(ss_ctx *ctx, int n, int s, const ss_c128 *sigma, const fl
 ss_status sigma_decode(ss_ctx *ctx, int n, int s, const float *y, const float *mean, const float *std, ss_c128 *sigma);
 
 ss_status transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
-                           double *T);
+                           const ss_c128 *psi0, const ss_c128 *gc, double *T);
+// Per-tile partial sums of the Caroli T_RL = Re Tr[Gamma_R G_n1 Gamma_L G_n1^H] from the corner gc:
+// caroli_rl_tiles(s) per instance at partial[inst * caroli_rl_tiles(s) + tile].
+int caroli_rl_tiles(int s);
+void launch_caroli_rl_partials(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
+                               double *partial);
 
 // Rates of plain MFMA, vector-FMA and copy kernels (see ss_measure_ceilings).
 ss_status measure_ceilings(ss_ctx *ctx, double *ceil);

@@ -14,6 +14,7 @@
 // leaves are W-row substitutions inside a tile and whose inner nodes are MFMA products.
 #include "lu.hpp"
 #include "tile.hpp"
+#include "tile32.hpp"
 
 #include <algorithm>
 #include <climits>
@@ -52,6 +53,7 @@ struct LuArgs {
   // null: the triangular-solve leaves substitute instead
   double2 *inv;
   long sInv;
+  int f32;  // products in FP32 (see LuDesc::f32)
 };
 
 // Base pointer and leading dimension for columns starting at c of system mat: columns >= n live in the
@@ -82,6 +84,7 @@ static LuArgs make_args(const LuDesc &d) {
   a.skip = d.skip; a.skip_shift = d.skip_shift;
   a.B = d.B; a.sB = d.sB; a.ldb = d.ldb;
   a.inv = nullptr; a.sInv = 0;
+  a.f32 = d.f32 ? 1 : 0;
   return a;
 }
 
@@ -623,6 +626,40 @@ __global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm(LuArgs a, int r
   });
 }
 
+// The same product with FP32 operands and accumulation on the FP32 matrix cores (the subtraction from
+// the FP64 stored value is done in FP64).
+using LuTile32 = TileCfg32<64, 64, 16, 2, 2>;
+using LuTileFlat32 = TileCfg32<32, 128, 16, 1, 4>;
+using LuTileNarrow32 = TileCfg32<64, 32, 16, 4, 1>;
+
+template <class T>
+__global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm32(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi,
+                                                                  int k_lo, int k_hi) {
+  static_assert(T::NT == 256, "load_perm assumes 256 threads");
+  __shared__ float lds[T::LDS_FLOATS];
+  __shared__ int sperm[kLuMaxN];
+  int tile, mat;
+  xcd_tile_order(tile, mat);
+  if (skipped(a, mat)) return;
+  double2 *M = a.M + (long)mat * a.sM;
+  const ColView cv = col_view(a, mat, c_lo);
+  load_perm(sperm, a.perm + (long)mat * a.sP, a.n);
+  const int tc = cdiv(c_hi - c_lo, T::BN);
+  const int m0 = r_lo + (tile / tc) * T::BM, n0 = c_lo + (tile % tc) * T::BN;
+  Acc32<T> acc;
+  acc.zero();
+  LdRowPerm la{M, a.ldm, sperm};
+  LdRowPerm lb{cv.p, cv.ld, sperm};
+  mma_loop32<T>(la, lb, m0, r_hi, n0, c_hi, k_lo, k_hi, acc, lds);
+  acc_foreach32<T>(acc, [&](int r, int c, double2 val) {
+    const int gr = m0 + r, gc = n0 + c;
+    if (gr < r_hi && gc < c_hi) {
+      double2 *p = cv.p + (long)sperm[gr] * cv.ld + gc;
+      *p = csub(*p, val);
+    }
+  });
+}
+
 // Leaf of the triangular solves: rows [r0, r0+w) of columns [c_lo, c_hi), in place, with the W x W
 // diagonal block at logical rows/columns r0 (unit lower if !kUpper, upper otherwise).
 template <int W, bool kUpper>
@@ -908,6 +945,22 @@ struct LuRun {
     if (r_lo >= r_hi || c_lo >= c_hi || k_lo >= k_hi) return;
     const double m_ = r_hi - r_lo, n_ = c_hi - c_lo, k_ = k_hi - k_lo;
     KernelScope ks_(ctx, "lu_gemm", 8.0 * m_ * n_ * k_ * d.nmat, 16.0 * (m_ * k_ + k_ * n_ + 2.0 * m_ * n_) * d.nmat);
+    if (a.f32) {
+      if (r_hi - r_lo <= LuTileFlat32::BM && c_hi - c_lo > LuTileFlat32::BN / 2) {
+        const int tiles = cdiv(c_hi - c_lo, LuTileFlat32::BN);
+        hipLaunchKernelGGL(k_lu_gemm32<LuTileFlat32>, dim3(tiles, d.nmat), dim3(LuTileFlat32::NT), 0, ctx->stream, a,
+                           r_lo, r_hi, c_lo, c_hi, k_lo, k_hi);
+      } else if (c_hi - c_lo <= LuTileNarrow32::BN && r_hi - r_lo > LuTileNarrow32::BM) {
+        const int tiles = cdiv(r_hi - r_lo, LuTileNarrow32::BM);
+        hipLaunchKernelGGL(k_lu_gemm32<LuTileNarrow32>, dim3(tiles, d.nmat), dim3(LuTileNarrow32::NT), 0, ctx->stream,
+                           a, r_lo, r_hi, c_lo, c_hi, k_lo, k_hi);
+      } else {
+        const int tiles = cdiv(r_hi - r_lo, LuTile32::BM) * cdiv(c_hi - c_lo, LuTile32::BN);
+        hipLaunchKernelGGL(k_lu_gemm32<LuTile32>, dim3(tiles, d.nmat), dim3(LuTile32::NT), 0, ctx->stream, a, r_lo,
+                           r_hi, c_lo, c_hi, k_lo, k_hi);
+      }
+      return;
+    }
     if (r_hi - r_lo <= LuTileFlat::BM && c_hi - c_lo > LuTileFlat::BN / 2) {
       const int tiles = cdiv(c_hi - c_lo, LuTileFlat::BN);
       hipLaunchKernelGGL(k_lu_gemm<LuTileFlat>, dim3(tiles, d.nmat), dim3(LuTileFlat::NT), 0, ctx->stream, a, r_lo,

@@ -30,6 +30,9 @@ struct LuDesc {
   double2 *B = nullptr;
   long sB = 0;
   int ldb = 0;
+  // products of the recursive factorization and of the triangular solves on the FP32 matrix cores
+  // (operands rounded to FP32, FP32 accumulation, FP64 storage); panels, pivots and leaves stay FP64
+  bool f32 = false;
 };
 
 // Default panel width of the factorization for order n (32 up to n = 1024, 8 up to 2048); a context

@@ -277,12 +277,13 @@ ss_status apply_obc_ragged(ss_ctx *ctx, const RaggedBatch &rb, const ss_c128 *Q,
 using TrTile = TileCfg<32, 32, 16, 2, 2>;
 
 // per (instance, direction, tile): partial sum of Re[(Gam_a G)_ij conj((G Gam_b)_ij)]
-__global__ void __launch_bounds__(TrTile::NT) k_trans(const double2 *gcp, const double2 *sigma, int s,
+// Directions dir0 + blockIdx.y; partial sums at [inst][blockIdx.y][tile].
+__global__ void __launch_bounds__(TrTile::NT) k_trans(const double2 *gcp, const double2 *sigma, int s, int dir0,
                                                        double *partial) {
   using T = TrTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ double red[T::NT / 64];
-  const int inst = blockIdx.z, dir = blockIdx.y;  // dir 0: T_LR with G_1n; dir 1: T_RL with G_n1
+  const int inst = blockIdx.z, dir = dir0 + blockIdx.y;  // dir 0: T_LR with G_1n; dir 1: T_RL with G_n1
   const int tiles = cdiv(s, T::BM);
   const int m0 = (blockIdx.x / tiles) * T::BM, n0 = (blockIdx.x % tiles) * T::BN;
   const long ss2 = (long)s * s;
@@ -315,7 +316,7 @@ __global__ void __launch_bounds__(TrTile::NT) k_trans(const double2 *gcp, const 
   if (threadIdx.x == 0) {
     double t = 0.0;
     for (int w = 0; w < T::NT / 64; ++w) t += red[w];
-    partial[((long)inst * 2 + dir) * gridDim.x + blockIdx.x] = t;
+    partial[((long)inst * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = t;
   }
 }
 
@@ -340,9 +341,17 @@ static void launch_transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc
   const int tiles = cdiv(s, TrTile::BM);
   const int ntile = tiles * tiles;
   hipLaunchKernelGGL(k_trans, dim3(ntile, 2, batch), dim3(TrTile::NT), 0, ctx->stream, (const double2 *)gc,
-                     (const double2 *)sigma, s, partial);
+                     (const double2 *)sigma, s, 0, partial);
   hipLaunchKernelGGL(k_trans_sum, dim3(cdiv(2 * batch, 256)), dim3(256), 0, ctx->stream, (const double *)partial,
                      ntile, T, 2 * batch);
+}
+
+int caroli_rl_tiles(int s) { return cdiv(s, TrTile::BM) * cdiv(s, TrTile::BM); }
+
+void launch_caroli_rl_partials(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
+                               double *partial) {
+  hipLaunchKernelGGL(k_trans, dim3(caroli_rl_tiles(s), 1, batch), dim3(TrTile::NT), 0, ctx->stream,
+                     (const double2 *)gc, (const double2 *)sigma, s, 1, partial);
 }
 
 ss_status transmission(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma, double *T) {

@@ -503,15 +503,38 @@ ss_status injection_left(ss_ctx *ctx, int batch, int s, const ss_c128 *sigma, do
   return check_launch(ctx, "injection_left");
 }
 
+// T[i] = sum of the psi partials + (sum of the Caroli partials - sum of the psi0 partials)
+__global__ void k_sum_tail(const double *pp, int np, const double *pc, int nc, const double *p0, double *out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double t = 0.0, c = 0.0, t0 = 0.0;
+  for (int k = 0; k < np; ++k) t += pp[(long)i * np + k];
+  for (int k = 0; k < nc; ++k) c += pc[(long)i * nc + k];
+  for (int k = 0; k < np; ++k) t0 += p0[(long)i * np + k];
+  out[i] = t + (c - t0);
+}
+
 ss_status transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi, const ss_c128 *sigma,
-                           double *T) {
+                           const ss_c128 *psi0, const ss_c128 *gc, double *T) {
   const int ntile = cdiv(s, TpTile::BM) * cdiv(m, TpTile::BN);
+  const bool tail = psi0 != nullptr && gc != nullptr;
+  const int nc = tail ? caroli_rl_tiles(s) : 0;
   void *wP;
-  SS_TRY(workspace(ctx, kSlotMisc, sizeof(double) * (size_t)batch * ntile, &wP));
+  SS_TRY(workspace(ctx, kSlotMisc, sizeof(double) * (size_t)batch * (tail ? 2 * ntile + nc : ntile), &wP));
+  double *pp = (double *)wP, *p0 = pp + (size_t)batch * ntile, *pc = p0 + (size_t)batch * ntile;
   hipLaunchKernelGGL(k_trans_psi, dim3(ntile, batch), dim3(TpTile::NT), 0, ctx->stream, (const double2 *)psi,
-                     (const double2 *)sigma, nb, s, m, (double *)wP);
-  hipLaunchKernelGGL(k_sum_rows, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const double *)wP, ntile, T,
-                     batch);
+                     (const double2 *)sigma, nb, s, m, pp);
+  if (!tail) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const double *)pp, ntile, T,
+                       batch);
+    return check_launch(ctx, "transmission_psi");
+  }
+  // psi0 holds one block row per instance: the last block row of the unrefined psi
+  hipLaunchKernelGGL(k_trans_psi, dim3(ntile, batch), dim3(TpTile::NT), 0, ctx->stream, (const double2 *)psi0,
+                     (const double2 *)sigma, 1, s, m, p0);
+  launch_caroli_rl_partials(ctx, batch, s, gc, sigma, pc);
+  hipLaunchKernelGGL(k_sum_tail, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, (const double *)pp, ntile,
+                     (const double *)pc, nc, (const double *)p0, T, batch);
   return check_launch(ctx, "transmission_psi");
 }
 

@@ -70,7 +70,7 @@ __device__ __forceinline__ double2 *xslot(const SweepArgs &a, int mat, int t) {
 }
 
 using FormTile = TileCfg<64, 64, 16, 2, 2>;
-using FormTile32 = TileCfg32<64, 64, 32, 2, 2>;
+using FormTile32 = TileCfg32<64, 64, 16, 2, 2>;
 static_assert(FormTile32::LDS_FLOATS <= 2 * FormTile::LDS_DOUBLES, "shared staging buffer too small");
 
 // acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in FP64 (kF32 == false) or with FP32 operands
@@ -93,7 +93,7 @@ __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0,
 
 // Forms [D | RHS] of step t for every system; fold the previous step's zero pivot into `code`.
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(kF32 ? 1 : 3)))
+__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES
 k_form(SweepArgs a, int t) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
@@ -199,7 +199,7 @@ __global__ void k_code_init(int *code, int n) {
 
 // Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(kF32 ? 1 : 3)))
+__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES
 k_chain(SweepArgs a, int u) {
   using T = FormTile;
   __shared__ double lds[T::LDS_DOUBLES];
@@ -280,6 +280,7 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
   d.sX = (long)a.nb * ss2;
   d.xoff = xoff;
   d.ldx = s;
+  d.f32 = prec == SS_PREC_FP32;
 
   double2 *F = nullptr;
   int *P = nullptr;

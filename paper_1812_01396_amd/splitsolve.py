@@ -120,7 +120,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_injection_left.restype = I
     lib.ss_refine_psi.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, P, P, I, P, P, D, I, P, P]
     lib.ss_refine_psi.restype = I
-    lib.ss_transmission_psi.argtypes = [P, I, I, I, I, P, P, P]
+    lib.ss_transmission_psi.argtypes = [P, I, I, I, I, P, P, P, P, P]
     lib.ss_transmission_psi.restype = I
     lib.ss_plan_create.argtypes = [P, I, ctypes.POINTER(_Instance), ctypes.POINTER(_PlanOpts), P, P,
                                    ctypes.POINTER(P)]
@@ -426,14 +426,22 @@ def ss_refine_psi(ctx: Context, Hd, Hu, Sd, Su, E, Q, sigma, inj, psi, kidx=None
     return psi, iters, resid
 
 
-def ss_transmission_psi(ctx: Context, psi, sigma, T=None):
-    """T = Re Tr[psi_nb^H Gamma_R psi_nb] for psi injected from the left.  Returns T [batch] float64."""
+def ss_transmission_psi(ctx: Context, psi, sigma, T=None, psi0=None, gc=None):
+    """T = Re Tr[psi_nb^H Gamma_R psi_nb] for psi injected from the left; with psi0 (the last block row of
+    the unrefined psi, [batch, s, m]) and gc (the corner of G^R that came with it) the part of Gamma_L
+    outside the injection factor is added back (see splitsolve.h).  Returns T [batch] float64."""
     dev = ctx.device
     batch, nb, s, m = psi.shape
     _need(psi, torch.complex128, dev, "psi")
     _need(sigma, torch.complex128, dev, "sigma", (batch, 2, s, s))
+    if (psi0 is None) != (gc is None):
+        raise ValueError("psi0 and gc are given together or not at all")
+    if psi0 is not None:
+        _need(psi0, torch.complex128, dev, "psi0", (batch, s, m))
+        _need(gc, torch.complex128, dev, "gc", (batch, 2 * s, 2 * s))
     T = T if T is not None else torch.empty(batch, dtype=torch.float64, device=dev)
-    ctx.check(ctx.lib.ss_transmission_psi(ctx.handle, batch, nb, s, m, _ptr(psi), _ptr(sigma), _ptr(T)))
+    ctx.check(ctx.lib.ss_transmission_psi(ctx.handle, batch, nb, s, m, _ptr(psi), _ptr(sigma), _ptr(psi0),
+                                          _ptr(gc), _ptr(T)))
     return T
 
 

@@ -5,7 +5,8 @@
   the full open system (ss_refine_psi) brings it to <= 1e-10 of the oracle's direct solve.
 * T from the refined psi (ss_transmission_psi) matches the oracle's Caroli T to 1e-8, including a
   perfect crystal at an energy next to an eigenvalue of the closed device, where the plain SMW route
-  loses digits to the closed device's conditioning.
+  loses digits to the closed device's conditioning, and an injection truncated to the open channels
+  with the rest of Gamma_L added back through the corner of G^R.
 """
 import numpy as np
 import pytest
@@ -33,7 +34,7 @@ def ctx():
     c.close()
 
 
-def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True, absorb=0.0):
+def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True, absorb=0.0, inj_tol=0.0):
     import paper_1812_01396_amd as ss
     hd, hu, sd, su = (_dev(np.stack([getattr(i, f) for i in insts])) for f in ("Hd", "Hu", "Sd", "Su"))
     leads = [_dev(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01")]
@@ -42,7 +43,7 @@ def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True, absorb
     q, info_q = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E_d, kidx=k_d, prec=prec, keep_factors=True,
                                          absorb=absorb)
     if inj is None:
-        inj_d, rank = ss.ss_injection_left(ctx, sig, mmax)
+        inj_d, rank = ss.ss_injection_left(ctx, sig, mmax, tol=inj_tol)
     else:
         inj_d, rank = _dev(inj), None
     psi, gc, info_o = ss.ss_apply_obc(ctx, q, sig, inj=inj_d, absorb=absorb)
@@ -54,6 +55,7 @@ def _run(ctx, insts, Es, kidx, eta, prec, inj=None, mmax=16, refine=True, absorb
         out.update(iters=iters, resid=resid)
     out["psi"] = psi
     out["T_psi"] = ss.ss_transmission_psi(ctx, psi, sig)
+    out["T_tail"] = ss.ss_transmission_psi(ctx, psi, sig, psi0=psi0[:, -1].contiguous(), gc=gc)
     torch.cuda.synchronize()
     for i in (info_s, info_q, info_o):
         assert int((i != 0).sum()) == 0
@@ -109,6 +111,25 @@ def test_transmission_from_refined_psi(ctx, prec):
         ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
                                        inst.S01, E, eta, want_q=False)
         assert abs(out["T_psi"][b] - ref["t_rl"]) <= 1e-8 * max(1.0, ref["t_rl"]), (E, out["T_psi"][b], ref)
+
+
+@pytest.mark.parametrize("prec,absorb", [(0, 1.0), (1, 1.0), (1, 0.0)])
+def test_transmission_tail_of_truncated_injection(ctx, prec, absorb):
+    """Injection truncated to the open channels (pivoted Cholesky stopped at 1e-5 of the largest pivot):
+    T from psi alone misses the broadening tail of Gamma_L (~1e-6 here), and with the tail added back
+    through the corner of G^R it matches the oracle's Caroli T_RL (1e-10 in FP64, 1e-8 with FP32
+    products, whose corner is ~1e-6 accurate but only weighs the small tail)."""
+    inst = synth.random_btd(5, 40, seed=909)
+    Es = np.array([-0.5, 0.1, 0.6])
+    eta = 1e-8
+    out = _run(ctx, [inst], Es, np.zeros(3, np.int32), eta, prec, mmax=12, absorb=absorb, inj_tol=1e-5)
+    for b, E in enumerate(Es):
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00,
+                                       inst.S01, E, eta, want_q=False)
+        assert 1 <= out["rank"][b] < 12
+        assert abs(out["T_psi"][b] - ref["t_rl"]) > 1e-7        # the tail is visible without the correction
+        tol = 1e-10 if prec == 0 else 1e-8
+        assert abs(out["T_tail"][b] - ref["t_rl"]) <= tol * max(1.0, ref["t_rl"]), (E, out["T_tail"][b], ref["t_rl"])
 
 
 def test_crystal_near_closed_device_eigenvalue(ctx):
