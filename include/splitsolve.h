@@ -95,7 +95,7 @@ size_t ss_workspace_bytes(const ss_ctx *ctx);
  * them.  Families: "form" (diagonal block formation and product of the recursion),
  * "chain" (Q_i = -X_i Q_{i-1}), "panel" (LU panel factorization), "lu_gemm" (LU trailing and
  * triangular-solve products), "trsm" (triangular-solve leaves), "dec_update" (decimation pass
- * products), "obc" (corner system and psi products), "trans" (transmission). */
+ * products), "obc" (corner system and psi products), "trans" (transmission), "obs" (observables). */
 ss_status ss_kernel_timer(ss_ctx *ctx, const char *family);
 /* Measured ceilings of this GPU (a profiling aid, the denominators the roofline fractions are checked
  * against): ceil (HOST pointer, 4 doubles) receives the FP64 matrix-core rate (TFLOP/s,
@@ -263,6 +263,24 @@ ss_status ss_refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kid
  * error of a low-precision gc enters T only in proportion to it. */
 ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, const ss_c128 *psi,
                               const ss_c128 *sigma, const ss_c128 *psi0, const ss_c128 *gc, double *T);
+
+/* ---------------------------------------------------------------- observables
+ * Sec. 2B: the charge and current densities follow from the wave function once Eq. (wf) is solved at
+ * every energy and momentum (Sec. 5C shows the electron distribution, the current map and the spectral
+ * current).  For psi [batch][nb][s][m] injected from the left lead (b' = [W_L; 0], so that
+ * psi psi^H = G Gamma_L G^H), with A = E S - H of the instance's (H, S) set (kidx as in the calls above):
+ *     density [batch][nb][s]:  n_mu = Re sum_c psi_{mu c} conj((S psi)_{mu c})   (Mulliken: the basis is
+ *                              non-orthogonal, n_mu = Re (psi psi^H S)_{mu mu})
+ *     current [batch][nb-1]:   J_i = 2 Im Tr[psi_i^H A_{i,i+1} psi_{i+1}]        (units e/h per spin)
+ * Either output may be NULL.  Inside the device (E S - H) psi vanishes row block by row block, so J_i
+ * is the same at every interface; for b' = [W_L; 0] it equals the transmission T_RL.  Neither depends on
+ * the factor W_L chosen.  Only S and the upper blocks of H are read; H_diag may be NULL. */
+ss_status ss_observables(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int m,
+                         const ss_c128 *psi, double *density, double *current);
+/* Energy (and momentum) integral as a weighted sum over instances: out[j] = sum_b w[b] x[b][j] for
+ * x [batch][n] (for instance the density above with w = quadrature weight x Fermi occupation / (2 pi));
+ * summed in instance order. */
+ss_status ss_energy_integral(ss_ctx *ctx, int batch, int n, const double *w, const double *x, double *out);
 
 /* ---------------------------------------------------------------- learned warm start
  * The decimation takes no starting iterate; Newton's method on the fixed-point equation of the

@@ -16,6 +16,8 @@ Contents (each function cites the passage of the paper it follows):
   (Sec. 3B, Step 1), G^R corner blocks and psi from a direct solve of T = A - Sigma (Sec. 2B,
   Eq. (negf)/(wf)), the SMW quantities R, z (Sec. 3B, Eq. (x)) and the Caroli transmission.
 * ``bands``: open-channel count from the lead band structure (independent physics pin).
+* ``observables``: orbital density and bond current from psi and their energy integral (Sec. 2B: the
+  charge and current densities follow from c(E) once Eq. (wf) is solved over the (E, k) grid).
 * ``warmstart``: Newton's method on the self-energy's fixed-point equation with the Stein correction by
   the Kronecker system or Smith's doubling, and the float64 forward/backward passes and Adam update of
   the multilayer perceptron that predicts the starting iterate.
@@ -23,4 +25,4 @@ Contents (each function cites the passage of the paper it follows):
 Parity is pinned for every function here by the ``-m "not gpu"`` tests (closed forms, brute force,
 invariants, band counting).  No function is "parity unpinned".
 """
-from . import bands, linalg, selfenergy, transport, warmstart  # noqa: F401
+from . import bands, linalg, observables, selfenergy, transport, warmstart  # noqa: F401

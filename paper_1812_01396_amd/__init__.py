@@ -15,6 +15,8 @@ from .splitsolve import (  # noqa: F401
     SS_PREC_FP32,
     SS_PREC_FP64,
     ss_apply_obc,
+    ss_energy_integral,
+    ss_observables,
     ss_injection_left,
     ss_lead_selfenergy,
     ss_lead_selfenergy_warm,

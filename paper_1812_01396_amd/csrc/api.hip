@@ -334,6 +334,26 @@ ss_status ss_transmission_psi(ss_ctx *ctx, int batch, int nb, int s, int m, cons
   return transmission_psi(ctx, batch, nb, s, m, psi, sigma, psi0, gc, T);
 }
 
+ss_status ss_observables(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int m,
+                         const ss_c128 *psi, double *density, double *current) {
+  SS_TRY(enter(ctx));
+  if (!hs || batch < 0 || m < 1 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
+    return fail(ctx, SS_ERR_ARG, "ss_observables: size out of range");
+  if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_observables: s > SS_MAX_S");
+  if (batch == 0 || (!density && !current)) return SS_OK;
+  if (!hs->S_diag || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)) || !E || !psi)
+    return fail(ctx, SS_ERR_ARG, "ss_observables: null pointer");
+  return observables(ctx, hs, batch, kidx, E, m, psi, density, current);
+}
+
+ss_status ss_energy_integral(ss_ctx *ctx, int batch, int n, const double *w, const double *x, double *out) {
+  SS_TRY(enter(ctx));
+  if (batch < 0 || n < 0) return fail(ctx, SS_ERR_ARG, "ss_energy_integral: size out of range");
+  if (n == 0) return SS_OK;
+  if (!out || (batch > 0 && (!w || !x))) return fail(ctx, SS_ERR_ARG, "ss_energy_integral: null pointer");
+  return energy_integral(ctx, batch, n, w, x, out);
+}
+
 // ---------------------------------------------------------------- learned warm start
 
 static bool dims_ok(int nlayer, const int *dims) {

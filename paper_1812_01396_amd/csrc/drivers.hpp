@@ -78,6 +78,10 @@ int caroli_rl_tiles(int s);
 void launch_caroli_rl_partials(ss_ctx *ctx, int batch, int s, const ss_c128 *gc, const ss_c128 *sigma,
                                double *partial);
 
+ss_status observables(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, int m,
+                      const ss_c128 *psi, double *density, double *current);
+ss_status energy_integral(ss_ctx *ctx, int batch, int n, const double *w, const double *x, double *out);
+
 // Rates of plain MFMA, vector-FMA and copy kernels (see ss_measure_ceilings).
 ss_status measure_ceilings(ss_ctx *ctx, double *ceil);
 

@@ -29,7 +29,7 @@ EXPORTS = (
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
-    "ss_lead_selfenergy_warm",
+    "ss_lead_selfenergy_warm", "ss_observables", "ss_energy_integral",
 )
 
 
@@ -154,6 +154,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_sigma_encode.restype = I
     lib.ss_sigma_decode.argtypes = [P, I, I, P, P, P, P]
     lib.ss_sigma_decode.restype = I
+    lib.ss_observables.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, I, P, P, P]
+    lib.ss_observables.restype = I
+    lib.ss_energy_integral.argtypes = [P, I, I, P, P, P]
+    lib.ss_energy_integral.restype = I
     lib.ss_lead_selfenergy_warm.argtypes = [P, I, I, I, P, P, P, P, P, P, D, P, D, I, I, P, P, P, P, P]
     lib.ss_lead_selfenergy_warm.restype = I
     _lib = lib
@@ -657,3 +661,33 @@ def ss_lead_selfenergy_warm(ctx: Context, H00, H01, S00, S01, E, eta: float, sig
                                               _ptr(kidx), _ptr(E), eta, _ptr(sigma_init), tol, max_newton, smith_steps,
                                               _ptr(sigma), _ptr(it_n), _ptr(it_d), _ptr(resid), _ptr(info)))
     return sigma, it_n, it_d, resid, info
+
+
+def ss_observables(ctx: Context, Hd, Hu, Sd, Su, E, psi, kidx=None, density=True, current=True):
+    """Orbital density [batch, nb, s] and bond currents [batch, nb - 1] of psi (see ss_observables in
+    splitsolve.h); either may be switched off (None returned)."""
+    dev = ctx.device
+    btd, nk, nb, s = _btd(Hd, Hu, Sd, Su, dev)
+    batch = E.numel()
+    m = psi.shape[-1]
+    _need(E, torch.float64, dev, "E")
+    _need(psi, torch.complex128, dev, "psi", (batch, nb, s, m))
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+    dens = torch.empty(batch, nb, s, dtype=torch.float64, device=dev) if density else None
+    cur = torch.empty(batch, max(nb - 1, 0), dtype=torch.float64, device=dev) if current else None
+    ctx.check(ctx.lib.ss_observables(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E), m, _ptr(psi),
+                                     _ptr(dens), _ptr(cur) if (cur is not None and nb > 1) else None))
+    return dens, cur
+
+
+def ss_energy_integral(ctx: Context, w, x, out=None):
+    """out[j] = sum_b w[b] x[b, j] (x [batch, ...] float64, summed over the leading axis)."""
+    dev = ctx.device
+    batch = x.shape[0]
+    n = int(x[0].numel()) if batch > 0 else 0
+    _need(w, torch.float64, dev, "w", (batch,))
+    _need(x, torch.float64, dev, "x")
+    out = out if out is not None else torch.empty(x.shape[1:], dtype=torch.float64, device=dev)
+    ctx.check(ctx.lib.ss_energy_integral(ctx.handle, batch, n, _ptr(w), _ptr(x), _ptr(out)))
+    return out
