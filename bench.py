@@ -51,8 +51,8 @@ WORKLOADS = {
     "dft1024": dict(s=1024, nb=60, n_e=32, e_lo=-5.0, e_hi=5.0, ks=[np.pi / 3], seed=2, eta=1e-8, m=32, chunk=32,
                     absorb=1.0),
 }
-# oracle transmissions of every instance, written by tests/golden/make_golden_<workload>.py (oracle only)
-GOLDEN_T = {"dft512": os.path.join(ROOT, "tests", "golden", "dft512_transmission.txt")}
+# oracle transmissions of every instance, written by tests/golden/make_golden_slab.py (oracle only)
+GOLDEN_T = {w: os.path.join(ROOT, "tests", "golden", f"{w}_transmission.txt") for w in ("dft512", "dft1024")}
 FP32_PEAK_TFLOPS = 157.3  # MI355X dense FP32 matrix, datasheet
 # kernel families of the first/last-column recursion (Step 1)
 RECURSION_FAMILIES = ",form,chain,panel,lu_gemm,trsm,"
@@ -666,6 +666,37 @@ class Pipeline:
         self.ctx.kernel_timer(None)
         return wall, kms
 
+    def observables(self):
+        """Orbital density and bond currents of every instance's psi (ss_observables, after a step), timed
+        with HIP events on the main stream, and their energy integral with trapezoid weights and a Fermi
+        occupation at mu = 0, kT = 0.025 (the quadrature is an input of the library call).  Current
+        conservation is reported as the largest spread of J_i over the interfaces of one instance."""
+        ss, torch, w = self.ss, self.torch, self.w
+        s, nb, m = w["s"], w["nb"], w["m"]
+        dE = float(self.E_np[1] - self.E_np[0]) if len(self.E_np) > 1 else 1.0
+        ne = w["n_e"]
+        wt = np.full(len(self.E_np), dE / (2 * np.pi) / len(w["ks"]))
+        wt[np.arange(len(self.E_np)) % ne == 0] *= 0.5
+        wt[np.arange(len(self.E_np)) % ne == ne - 1] *= 0.5
+        wt *= 0.5 * (1.0 - np.tanh(0.5 * self.E_np / 0.025))
+        wt_d = torch.as_tensor(wt, dtype=torch.float64, device=self.dev)
+        torch.cuda.synchronize()
+        self.ctx.kernel_timer("obs")
+        dens, cur = ss.ss_observables(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E, self.psi, kidx=self.kidx)
+        ms, launches = self.ctx.kernel_timer_read()[:2]
+        self.ctx.kernel_timer(None)
+        n_int = ss.ss_energy_integral(self.ctx, wt_d, dens)
+        torch.cuda.synchronize()
+        cur_np = cur.cpu().numpy()
+        spread = float(np.max((cur_np.max(axis=1) - cur_np.min(axis=1)) / np.maximum(np.abs(cur_np).max(axis=1), 1e-300)))
+        n_b = self.n
+        # density: the diagonal and off-diagonal S blocks times psi (3 nb - 2 products of s x s x m per
+        # instance); current: nb - 1 products
+        flops = 8.0 * s * s * m * n_b * ((3 * nb - 2) + (nb - 1))
+        return dict(ms=round(ms, 3), launches=int(launches), tflops=round(flops / (ms * 1e-3) / 1e12, 3),
+                    frac_fp64_peak=round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
+                    current_spread_max=spread, integrated_density_sum=float(n_int.sum().item()))
+
     def _fp64_fallback(self, c0, c1):
         """Instances whose refinement from the FP32-product factors did not reach the tolerance (pivot
         blocks too ill-conditioned for FP32 products) are solved again with FP64 products and refined."""
@@ -696,6 +727,60 @@ class Pipeline:
         self.ir_resid[idx] = res_b
 
 
+def run_spike(args):
+    """Step 1 for a small batch (the first --spike-batch instances of the workload) with the plain
+    recursion and through 2, 4, 8, 16 partitions merged by SPIKE: wall time per call and Q against the
+    plain recursion's."""
+    import torch
+
+    import paper_1812_01396_amd as ss
+
+    w, insts, E_np, kidx_np, _ = build_inputs(args.workload)
+    nb, s = w["nb"], w["s"]
+    dev = torch.device("cuda", 0)
+
+    def t(a, dt=torch.complex128):
+        return torch.as_tensor(np.ascontiguousarray(a), dtype=dt).to(dev)
+
+    hd, hu, sd, su = (t(np.stack([getattr(i, f) for i in insts])) for f in ("Hd", "Hu", "Sd", "Su"))
+    nbat = min(args.spike_batch, len(E_np))
+    E = t(E_np[:nbat], torch.float64)
+    kidx = t(kidx_np[:nbat], torch.int32)
+    ctx = ss.Context(0)
+    q_ref, _ = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E, kidx=kidx, absorb=w["absorb"])
+    q = torch.empty_like(q_ref)
+    rows = []
+    for p in [1, 2, 4, 8, 16]:
+        if p > nb:
+            break
+        def call():
+            if p == 1:
+                ss.ss_precompute_columns(ctx, hd, hu, sd, su, E, kidx=kidx, Q=q, absorb=w["absorb"], validate=False)
+            else:
+                ss.ss_precompute_columns_spike(ctx, hd, hu, sd, su, E, p, kidx=kidx, Q=q, absorb=w["absorb"])
+        for _ in range(args.warmup):
+            call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            call()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / args.steps
+        err = float(((q - q_ref).reshape(nbat, -1).norm(dim=1) / q_ref.reshape(nbat, -1).norm(dim=1)).max())
+        f = nbat * sweep_flops(nb, s) + (nbat * 16.0 * nb * s**3 * np.log2(p) if p > 1 else 0.0)
+        rows.append(dict(nparts=p, ms=round(ms, 3), solves_per_s=round(nbat / (ms * 1e-3), 3),
+                         tflops=round(f / (ms * 1e-3) / 1e12, 3), q_rel_diff_vs_plain=err))
+    ctx.close()
+    best = min(rows, key=lambda r: r["ms"])
+    out = {"metric": "(E,k) Step-1 solves/sec, small batch", "value": best["solves_per_s"], "unit": "solves/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c128", "data": "synthetic",
+           "config": {"workload": args.workload + "-spike", "s": s, "nb": nb, "instances": nbat,
+                      "absorb": w["absorb"], "best_nparts": best["nparts"]},
+           "partitions": rows, "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -724,6 +809,9 @@ def main():
                     help="only print a per-kernel summary of a rocprofv3 kernel trace (*_results.db or "
                          "*kernel_trace.csv) and exit (no GPU needed)")
     ap.add_argument("--trace-steps", type=int, default=1, help="--summarize-trace: steps the trace covers")
+    ap.add_argument("--spike-batch", type=int, default=0,
+                    help="time Step 1 for this many instances with the plain recursion and through 2-16 SPIKE "
+                         "partitions (small batches) and exit")
     ap.add_argument("--cpu-sample", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -754,6 +842,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": src.numel() * 8, "copy_bytes_written": dst.numel() * 8, "launches": 3}))
         return
+    if args.spike_batch > 0:
+        return run_spike(args)
     if args.workload == "uneven256":
         return run_uneven(args)
     if args.workload == "learned":
@@ -776,10 +866,12 @@ def main():
     timed_ctx.kernel_timer(None)
     # one more (untimed) step with the recursion's kernels bracketed by HIP events: recursion TFLOP/s
     rec_ms, rec_alone_wall, rec_alone_kms = [], None, None
+    obs = None
     if not args.no_extra:
         pipe.run(recursion_ms=rec_ms)
         torch.cuda.synchronize()
         rec_alone_wall, rec_alone_kms = pipe.recursion_alone()
+        obs = pipe.observables()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
     mixed = args.mode == "mixed"
@@ -846,6 +938,7 @@ def main():
         "roofline": roof,
         # the recursion's algorithmic flops / the summed duration of its kernels (form, chain, LU) in one
         # step, measured with HIP events while the self-energies run beside it on the second stream
+        "observables": obs,
         "recursion": None if args.no_extra else dict(kernel_ms=round(sum(rec_ms), 2),
                           tflops=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
                           frac_peak=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /

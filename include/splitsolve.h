@@ -180,6 +180,27 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
                                 const double *E, double absorb, int prec, int flags, ss_c128 *Q,
                                 int *info);
 
+/* Step 1 through partitions (Sec. 3B: the partitioned pre-processing and its recursive SPIKE merge,
+ * which the paper uses to spread one device over several GPUs; on one GPU it multiplies the systems a
+ * small batch offers to the lockstep recursion).  The same Q as ss_precompute_columns (to rounding),
+ * computed as follows: the nb blocks are cut into nparts consecutive partitions (a power of two, at
+ * most nb; the first nb % nparts partitions are one block longer), Alg. 1 runs on every partition of
+ * every instance as one batch (each partition a closed device of its own, with the absorbing shift on
+ * both of its end blocks: at a cut it broadens the closed partition's resonances as at the device's
+ * ends, and the merge takes it out again), and adjacent partitions are merged level by level
+ * (log2 nparts levels): each merge solves one interface system of order 2s per pair (LU with partial
+ * pivoting) and updates both halves' columns with products over all their rows.  The merges cost about
+ * 16 nb s^3 flops per level and instance, beside the recursion's ~53 nb s^3.  nparts = 1 is the plain
+ * recursion.  prec as ss_precompute_columns (no SS_KEEP_FACTORS).  Q [batch][nb][s][2s] as there;
+ * info [batch] (may be NULL): 0, or 1 + (i-1)*s + c for an exactly zero pivot in column c of the i-th
+ * diagonal system of a partition's recursion (i counted over the whole device), or 1 + la*s + c for one
+ * in column c of the interface system after (0-based) block la; the smallest such code.  Workspace: the
+ * partitions' recursion as for ss_precompute_columns plus a second Q-sized buffer and the interface
+ * systems.  The call uploads small host tables (it is not usable in sync-free mode). */
+ss_status ss_precompute_columns_spike(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx,
+                                      const double *E, double absorb, int prec, int nparts, ss_c128 *Q,
+                                      int *info);
+
 /* The block solver of Step 1 on its own: batched LU with partial pivoting (Alg. 1 solves every
  * D_i X_i = A_{i,i+1} through this factorization).
  *

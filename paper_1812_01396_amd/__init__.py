@@ -25,6 +25,7 @@ from .splitsolve import (  # noqa: F401
     ss_sigma_moments,
     ss_warm_features,
     ss_precompute_columns,
+    ss_precompute_columns_spike,
     ss_lu_factor,
     ss_refine_psi,
     ss_transmission,

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libsplitsolve.so")
 ARCH = os.environ.get("SS_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["api.hip", "lu.hip", "sweep.hip", "selfenergy.hip", "obc.hip", "refine.hip", "plan.hip", "mlp.hip", "warm.hip",
-           "ceilings.hip", "observables.hip"]
+           "ceilings.hip", "observables.hip", "spike.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}",

@@ -244,6 +244,25 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   return precompute_columns(ctx, hs, batch, kidx, E, absorb, prec, flags, Q, info);
 }
 
+ss_status ss_precompute_columns_spike(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
+                                      double absorb, int prec, int nparts, ss_c128 *Q, int *info) {
+  SS_TRY(enter(ctx));
+  if (!hs || batch < 0 || hs->nb < 1 || hs->s < 1 || hs->nk < 1)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: size out of range");
+  if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_precompute_columns_spike: s > SS_MAX_S");
+  if (nparts < 1 || nparts > hs->nb || (nparts & (nparts - 1)) != 0)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: nparts must be a power of two in [1, nb]");
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: unknown precision");
+  if (!(absorb >= 0.0) || !std::isfinite(absorb))
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: absorb must be finite and >= 0");
+  if (batch == 0) return SS_OK;
+  if (!hs->H_diag || !hs->S_diag || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)) || !E || !Q)
+    return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: null pointer");
+  ctx->fact_valid = false;
+  return precompute_spike(ctx, hs, batch, kidx, E, absorb, prec, nparts, Q, info);
+}
+
 ss_status ss_measure_ceilings(ss_ctx *ctx, double *ceil) {
   SS_TRY(enter(ctx));
   if (!ceil) return fail(ctx, SS_ERR_ARG, "ss_measure_ceilings: null output");

@@ -87,6 +87,7 @@ enum Slot {
   kSlotMlp,        // split-K partial products of the network
   kSlotMlpDz,      // back-propagated gradients
   kSlotLuInv,      // inverses of the LU's diagonal blocks (triangular-solve leaves)
+  kSlotSpike,      // partition tables, the second column buffer and the interface systems of the merges
   kNumSlots
 };
 

@@ -24,6 +24,9 @@ ss_status precompute_ragged(ss_ctx *ctx, const RaggedBatch &rb, double absorb, i
 
 ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E,
                              double absorb, int prec, int flags, ss_c128 *Q, int *info);
+// Step 1 through nparts partitions per instance and the recursive SPIKE merge of their columns.
+ss_status precompute_spike(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, const double *E, double absorb,
+                           int prec, int nparts, ss_c128 *Q, int *info);
 
 ss_status lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c128 *H00, const ss_c128 *H01,
                           const ss_c128 *S00, const ss_c128 *S01, const int *kidx, const double *E,

@@ -29,7 +29,7 @@ EXPORTS = (
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
-    "ss_lead_selfenergy_warm", "ss_observables", "ss_energy_integral",
+    "ss_lead_selfenergy_warm", "ss_observables", "ss_energy_integral", "ss_precompute_columns_spike",
 )
 
 
@@ -154,6 +154,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_sigma_encode.restype = I
     lib.ss_sigma_decode.argtypes = [P, I, I, P, P, P, P]
     lib.ss_sigma_decode.restype = I
+    lib.ss_precompute_columns_spike.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, D, I, I, P, P]
+    lib.ss_precompute_columns_spike.restype = I
     lib.ss_observables.argtypes = [P, ctypes.POINTER(_Btd), I, P, P, I, P, P, P]
     lib.ss_observables.restype = I
     lib.ss_energy_integral.argtypes = [P, I, I, P, P, P]
@@ -691,3 +693,22 @@ def ss_energy_integral(ctx: Context, w, x, out=None):
     out = out if out is not None else torch.empty(x.shape[1:], dtype=torch.float64, device=dev)
     ctx.check(ctx.lib.ss_energy_integral(ctx.handle, batch, n, _ptr(w), _ptr(x), _ptr(out)))
     return out
+
+
+def ss_precompute_columns_spike(ctx: Context, Hd, Hu, Sd, Su, E, nparts: int, kidx=None, Q=None, info=None,
+                                prec: int = SS_PREC_FP64, absorb: float = 0.0):
+    """Q as ss_precompute_columns, through nparts partitions per instance and their recursive SPIKE merge
+    (see splitsolve.h).  Returns (Q [batch, nb, s, 2s], info [batch])."""
+    dev = ctx.device
+    btd, nk, nb, s = _btd(Hd, Hu, Sd, Su, dev)
+    batch = E.numel()
+    _need(E, torch.float64, dev, "E")
+    if kidx is not None:
+        _need(kidx, torch.int32, dev, "kidx", (batch,))
+        _check_kidx(kidx, nk)
+    Q = Q if Q is not None else torch.empty(batch, nb, s, 2 * s, dtype=torch.complex128, device=dev)
+    _need(Q, torch.complex128, dev, "Q", (batch, nb, s, 2 * s))
+    info = info if info is not None else torch.empty(batch, dtype=torch.int32, device=dev)
+    ctx.check(ctx.lib.ss_precompute_columns_spike(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E),
+                                                  float(absorb), int(prec), int(nparts), _ptr(Q), _ptr(info)))
+    return Q, info
