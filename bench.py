@@ -542,6 +542,7 @@ class Pipeline:
 
         self.ss, self.torch = ss, torch
         self.mode = mode
+        self.prec = {"fp64": ss.SS_PREC_FP64, "mixed": ss.SS_PREC_FP32, "mixed-lu": ss.SS_PREC_FP32_LU}[mode]
         self.refine_tol = refine_tol
         self.accept_tol = accept_tol  # refined residual above this: the instance is redone in FP64
         self.fallback = 0
@@ -580,7 +581,7 @@ class Pipeline:
         self.info_o = torch.empty(nb_inst, dtype=torch.int32, device=dev)
         self.T_psi = torch.empty(nb_inst, dtype=torch.float64, device=dev)
         # mixed: last block row of the unrefined psi (with gc it carries the part of Gamma_L outside W_L)
-        self.psi0 = torch.empty(nb_inst, s, m, dtype=c128, device=dev) if mode == "mixed" else None
+        self.psi0 = torch.empty(nb_inst, s, m, dtype=c128, device=dev) if mode != "fp64" else None
         self.rank = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
         self.ir_iters = torch.zeros(nb_inst, dtype=torch.int32, device=dev)
         self.ir_resid = torch.zeros(nb_inst, dtype=torch.float64, device=dev)
@@ -612,7 +613,7 @@ class Pipeline:
 
         th = threading.Thread(target=run_sigma)
         th.start()
-        mixed = self.mode == "mixed"
+        mixed = self.mode != "fp64"
         for c0 in range(0, self.n, self.chunk):
             c1 = min(c0 + self.chunk, self.n)
             q = self.Qbuf[: c1 - c0]
@@ -620,7 +621,7 @@ class Pipeline:
                 self.ctx.kernel_timer(RECURSION_FAMILIES)
             ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
                                      kidx=self.kidx[c0:c1], Q=q, info=self.info_q[c0:c1], validate=False,
-                                     prec=ss.SS_PREC_FP32 if mixed else ss.SS_PREC_FP64, keep_factors=mixed,
+                                     prec=self.prec, keep_factors=mixed,
                                      absorb=self.absorb)
             if recursion_ms is not None:
                 recursion_ms.append(self.ctx.kernel_timer_read()[0])
@@ -650,7 +651,7 @@ class Pipeline:
         """Step 1 by itself (no self-energies beside it): wall time (ms) of ss_precompute_columns over
         all instances, and the summed duration of its kernels (HIP events)."""
         ss, torch = self.ss, self.torch
-        mixed = self.mode == "mixed"
+        mixed = self.mode != "fp64"
         torch.cuda.synchronize()
         self.ctx.kernel_timer(RECURSION_FAMILIES)
         t0 = time.perf_counter()
@@ -658,7 +659,7 @@ class Pipeline:
             c1 = min(c0 + self.chunk, self.n)
             ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1],
                                      kidx=self.kidx[c0:c1], Q=self.Qbuf[: c1 - c0], info=self.info_q[c0:c1],
-                                     validate=False, prec=ss.SS_PREC_FP32 if mixed else ss.SS_PREC_FP64,
+                                     validate=False, prec=self.prec,
                                      keep_factors=mixed, absorb=self.absorb)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3
@@ -791,7 +792,8 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="uneven256: default panel widths and chunks")
     ap.add_argument("--plan-mem-gib", type=float, default=0.0,
                     help="uneven256: chunk work memory (0: the device memory left after the inputs, less 4 GiB)")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "mixed-lu"],
+                    help="mixed: FP32 products in the block formations and the chain; mixed-lu: also in the LU")
     ap.add_argument("--absorb", type=float, default=-1.0,
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")
@@ -874,7 +876,7 @@ def main():
         obs = pipe.observables()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
-    mixed = args.mode == "mixed"
+    mixed = args.mode != "fp64"
     # the product's T: Caroli (T_LR, T_RL) in fp64 mode; T carried by the refined psi in mixed mode
     T_np = pipe.T.cpu().numpy()
     if mixed:

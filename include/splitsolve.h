@@ -144,9 +144,11 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
 /* Precision of the recursion's block products in ss_precompute_columns.  Storage is always FP64; the
  * LU panels (pivot search and elimination inside a panel), the triangular leaves, the corner system
  * and every residual are always FP64. */
-#define SS_PREC_FP64 0 /* complex FP64 products (FP64 matrix cores)                           */
-#define SS_PREC_FP32 1 /* complex FP32 products with FP32 accumulation: the block formations,   */
-                       /* the chain, and the LU's trailing and triangular-solve updates          */
+#define SS_PREC_FP64 0    /* complex FP64 products (FP64 matrix cores)                        */
+#define SS_PREC_FP32 1    /* complex FP32 products with FP32 accumulation in the block          */
+                          /* formations and the chain; the LU stays FP64                        */
+#define SS_PREC_FP32_LU 2 /* as SS_PREC_FP32, and the LU's trailing and triangular-solve        */
+                          /* updates in FP32 too (less accurate factors: more refinement passes) */
 
 /* flags of ss_precompute_columns */
 #define SS_KEEP_FACTORS 1 /* keep the first-column recursion's factors in the context for     */

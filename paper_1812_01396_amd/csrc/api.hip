@@ -235,7 +235,7 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   if (batch == 0) return SS_OK;
   if (!hs->H_diag || !hs->S_diag || !E || !Q || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)))
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null input or output pointer");
-  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32)
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown precision");
   if (flags & ~SS_KEEP_FACTORS) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown flags");
   if (!(absorb >= 0.0) || !std::isfinite(absorb))
@@ -252,7 +252,7 @@ ss_status ss_precompute_columns_spike(ss_ctx *ctx, const ss_btd *hs, int batch, 
   if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_precompute_columns_spike: s > SS_MAX_S");
   if (nparts < 1 || nparts > hs->nb || (nparts & (nparts - 1)) != 0)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: nparts must be a power of two in [1, nb]");
-  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32)
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: unknown precision");
   if (!(absorb >= 0.0) || !std::isfinite(absorb))
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: absorb must be finite and >= 0");

@@ -280,7 +280,7 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
   d.sX = (long)a.nb * ss2;
   d.xoff = xoff;
   d.ldx = s;
-  d.f32 = prec == SS_PREC_FP32;
+  d.f32 = prec == SS_PREC_FP32_LU;
 
   double2 *F = nullptr;
   int *P = nullptr;
@@ -289,7 +289,7 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
     SS_TRY(workspace(ctx, kSlotFactPerm, sizeof(int) * (size_t)total_blocks * s, (void **)&P));
   }
   ctx->fact_valid = false;
-  const bool f32 = prec == SS_PREC_FP32;
+  const bool f32 = prec == SS_PREC_FP32 || prec == SS_PREC_FP32_LU;
   hipLaunchKernelGGL(k_code_init, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a.code, batch);
   const int tiles = cdiv(s, FormTile::BM);
   for (int t = 0; t < nsteps; ++t) {

@@ -1,19 +1,21 @@
-"""Writes tests/golden/dft512_transmission.txt: the oracle's transmission for every instance of the
-s = 512 lattice-slab workload (calls only the oracle and the input generators).
+"""Writes tests/golden/<workload>_transmission.txt: the oracle's transmission for every instance of a
+lattice-slab workload (calls only the oracle and the input generators).
 
-Workload: the 8x8x8 lattice-slab cell of seed 1 at momenta k in {pi/8, 3pi/8, 5pi/8, 7pi/8}, a perfect
-crystal device of nb = 40 copies, leads = the same cell, 64 energies linspace(-5, 5, 64), eta = 1e-8;
-instance b has momentum index b // 64 and energy index b % 64 (256 instances).
+Workloads (perfect crystal devices: nb copies of the cell, leads = the same cell, eta = 1e-8):
+  dft512:  the 8x8x8 cell of seed 1, nb = 40, momenta k in {pi/8, 3pi/8, 5pi/8, 7pi/8}, 64 energies
+           linspace(-5, 5, 64); instance b has momentum index b // 64 and energy index b % 64 (256).
+  dft1024: the 8x8x16 cell of seed 2, nb = 60, k = pi/3, 32 energies linspace(-5, 5, 32) (32).
 
 Per instance the file holds the Caroli pair (T_LR, T_RL) of the oracle's direct solve of the open
 system (block Thomas on T = A - Sigma, decimation to 1e-14), the decimation passes, and the number of
 right-moving Bloch states N_ch(E) from the lead band structure (a perfect crystal transmits exactly
 N_ch up to O(eta)) with the smallest distance of E to a band on the q grid.
 
-    python tests/golden/make_golden_dft512.py [--workers 8] [--dense 2]
+    python tests/golden/make_golden_slab.py --workload dft512 [--workers 8] [--dense 2]
+    python tests/golden/make_golden_slab.py --workload dft1024 --workers 4 --threads 2
 
 --dense n additionally solves the first n instances of the largest |T - N_ch| densely (numpy's LU of
-the assembled 20480 x 20480 open-system matrix) and writes tests/golden/dft512_dense_check.txt: the
+the assembled open-system matrix, N = nb s) and writes tests/golden/<workload>_dense_check.txt: the
 block-Thomas and the dense transmissions side by side (a full-size check of the oracle itself).
 """
 import argparse
@@ -28,11 +30,28 @@ import numpy as np  # noqa: E402
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-S, NB, SEED, ETA, NQ = 512, 40, 1, 1e-8, 1024
-KS = [np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8]
-ENERGIES = np.linspace(-5.0, 5.0, 64)
-OUT = os.path.join(HERE, "dft512_transmission.txt")
-DENSE_OUT = os.path.join(HERE, "dft512_dense_check.txt")
+WORKLOADS = {
+    "dft512": dict(s=512, nb=40, seed=1, ks=[np.pi / 8, 3 * np.pi / 8, 5 * np.pi / 8, 7 * np.pi / 8], n_e=64),
+    "dft1024": dict(s=1024, nb=60, seed=2, ks=[np.pi / 3], n_e=32),
+}
+ETA, NQ = 1e-8, 1024
+S = NB = SEED = None
+KS = ENERGIES = OUT = DENSE_OUT = None
+
+
+def _configure(name):
+    global S, NB, SEED, KS, ENERGIES, OUT, DENSE_OUT
+    w = WORKLOADS[name]
+    S, NB, SEED, KS = w["s"], w["nb"], w["seed"], w["ks"]
+    ENERGIES = np.linspace(-5.0, 5.0, w["n_e"])
+    OUT = os.path.join(HERE, f"{name}_transmission.txt")
+    DENSE_OUT = os.path.join(HERE, f"{name}_dense_check.txt")
+
+
+def _init_worker(name, threads):
+    _configure(name)
+    import threadpoolctl
+    threadpoolctl.threadpool_limits(threads)
 
 _cells = {}
 
@@ -90,18 +109,22 @@ def main():
     from oracle import bands
 
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="dft512", choices=sorted(WORKLOADS))
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--threads", type=int, default=1, help="BLAS threads per worker")
     ap.add_argument("--dense", type=int, default=0)
     ap.add_argument("--skip-transport", action="store_true", help="reuse the existing transmission file")
     args = ap.parse_args()
+    _configure(args.workload)
     n = len(KS) * len(ENERGIES)
     if not args.skip_transport:
-        with Pool(args.workers) as pool:
-            bb = dict(pool.map(_bands, range(len(KS))))
+        with Pool(args.workers, initializer=_init_worker, initargs=(args.workload, args.threads)) as pool:
+            band_jobs = pool.map_async(_bands, range(len(KS)))  # beside the solves
             rows = {}
             for b, t_lr, t_rl, it in pool.imap_unordered(_solve, range(n)):
                 rows[b] = (t_lr, t_rl, it)
                 print(f"instance {b}: T_LR {t_lr:.12f} T_RL {t_rl:.12f}", flush=True)
+            bb = dict(band_jobs.get())
         lines = ["# b  E  k  T_LR  T_RL  decimation_passes  N_ch  min|E_n(q)-E|",
                  f"# s={S} nb={NB} seed={SEED} eta={ETA:g} crystal device; bands on {NQ} q points"]
         for b in range(n):
@@ -118,7 +141,8 @@ def main():
         import threadpoolctl
 
         lines = ["# b  T_LR(dense)  T_RL(dense)  T_LR(block Thomas)  T_RL(block Thomas)",
-                 "# dense LU of the assembled open-system matrix (N = 20480) for the instances of largest |T - N_ch|"]
+                 f"# dense LU of the assembled open-system matrix (N = {NB * S}) for the instances of largest "
+                 "|T - N_ch|"]
         for b in pick:
             with threadpoolctl.threadpool_limits(args.workers):
                 t_lr, t_rl = _dense(b)

@@ -3,11 +3,12 @@
 dft512: s = 512, nb = 40, 64 energies x 4 momenta (256 instances), all of them in one chunk of Q, the
 self-energies on a second stream, the absorbing boundary of the benchmark (absorb = 1).  Every
 instance's Caroli pair is compared with the oracle's, stored in tests/golden/dft512_transmission.txt
-(written by tests/golden/make_golden_dft512.py from the oracle alone), at 1e-8; sampled instances are
+(written by tests/golden/make_golden_slab.py from the oracle alone), at 1e-8; sampled instances are
 compared element by element (Sigma, corner of G^R, psi) with the oracle run here.  The device is a
 perfect crystal, so T is also the open-channel count (to O(eta)) and T_LR = T_RL.
 chain16: s = 16, nb = 32, all 64 energies against the stored channel counts.
 """
+import gc
 import os
 
 import numpy as np
@@ -35,6 +36,10 @@ def dft512():
     yield pipe
     pipe.ctx.close()
     pipe.ctx_s.close()
+    for k in list(vars(pipe)):  # drop the device tensors now: the next full-size module needs the memory
+        setattr(pipe, k, None)
+    gc.collect()
+    torch.cuda.empty_cache()
 
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "dft512_transmission.txt")

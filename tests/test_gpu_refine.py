@@ -76,7 +76,7 @@ def test_injection_factor_reproduces_gamma(ctx):
         assert 1 <= out["rank"][b] <= 24
 
 
-@pytest.mark.parametrize("prec,absorb", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0)])
+@pytest.mark.parametrize("prec,absorb", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0), (2, 1.0)])
 def test_refined_psi_matches_oracle(ctx, prec, absorb):
     """Refinement of psi on the open system from the kept factors, for the paper's split and for the
     absorbing one (the factors of A' and C' = Sigma + i*absorb*I)."""
@@ -95,7 +95,7 @@ def test_refined_psi_matches_oracle(ctx, prec, absorb):
         tol = max(1e-10, 10 * 2.0 ** -52 * selfenergy.decimation_conditioning(a0, a1, am1))
         e0 = _rel(out["psi0"][b], ref["psi"])
         e1 = _rel(out["psi"][b], ref["psi"])
-        if prec == 1:
+        if prec >= 1:
             assert e0 > 1e-9          # FP32 products: the unrefined psi is visibly less accurate
         assert e1 <= tol, (b, e0, e1, tol)
         assert out["resid"][b] <= 1e-12
@@ -113,7 +113,7 @@ def test_transmission_from_refined_psi(ctx, prec):
         assert abs(out["T_psi"][b] - ref["t_rl"]) <= 1e-8 * max(1.0, ref["t_rl"]), (E, out["T_psi"][b], ref)
 
 
-@pytest.mark.parametrize("prec,absorb", [(0, 1.0), (1, 1.0), (1, 0.0)])
+@pytest.mark.parametrize("prec,absorb", [(0, 1.0), (1, 1.0), (1, 0.0), (2, 1.0)])
 def test_transmission_tail_of_truncated_injection(ctx, prec, absorb):
     """Injection truncated to the open channels (pivoted Cholesky stopped at 1e-5 of the largest pivot):
     T from psi alone misses the broadening tail of Gamma_L (~1e-6 here), and with the tail added back
