@@ -156,3 +156,40 @@ def test_plan_small_memory_runs_one_instance_per_chunk(ctx, batch):
     assert np.abs(big.T.cpu().numpy() - small.T.cpu().numpy()).max() <= 1e-12
     big.close()
     small.close()
+
+
+def test_plan_uneven_workload_sizes_vs_oracle(ctx):
+    """One instance of each block size of the uneven 256-instance workload (s = 128, 256, 384, 512, 768, its
+    own cell, nb, E and k from that workload's generator, absorbing boundary 1) in one autotuned plan run as
+    the workload runs (its groups' graphs would exceed the node bound, so the groups enqueue from threads of
+    their own): T against the oracle's Caroli pair at 1e-8 (the workload's own bar), every code zero."""
+    import bench
+    import paper_1812_01396_amd as ss
+    specs, seen = [], set()
+    for spec in bench.uneven_specs():
+        if spec[0] not in seen:
+            seen.add(spec[0])
+            specs.append(spec)
+    assert sorted(seen) == [128, 256, 384, 512, 768]
+    items, cells = [], []
+    for spec in specs:
+        s, nb, E, k, _ = spec
+        cell = bench.uneven_cell(spec)
+        cells.append(cell)
+        inst = synth.device_from_cell(cell, nb)
+        items.append(ss.Instance(_dev(inst.Hd), _dev(inst.Hu), _dev(inst.Sd), _dev(inst.Su), *[_dev(x) for x in cell],
+                                 E))
+    print("uneven sizes:", [(s, nb) for s, nb, _, _, _ in specs], flush=True)
+    plan = ss.Plan(ctx, items, bench.UNEVEN["eta"], use_graph=False, autotune=True, absorb=bench.UNEVEN["absorb"])
+    plan.execute()
+    torch.cuda.synchronize()
+    T, info = plan.T.cpu().numpy(), plan.info.cpu().numpy()
+    plan.close()
+    assert (info[:, :3] == 0).all(), info
+    for i, spec in enumerate(specs):
+        s, nb, E, k, _ = spec
+        inst = synth.device_from_cell(cells[i], nb)
+        ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, *cells[i], E, bench.UNEVEN["eta"],
+                                       want_q=False)
+        for got, want in ((T[i, 0], ref["t_lr"]), (T[i, 1], ref["t_rl"])):
+            assert abs(got - want) <= 1e-8 * max(1.0, abs(want)), (spec[:2], got, want)
