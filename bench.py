@@ -195,6 +195,21 @@ def golden_errors(workload: str, T_gpu):
                 over_1e_8=int((err.max(axis=1) > 1e-8).sum()), over_1e_10=int((err.max(axis=1) > 1e-10).sum()))
 
 
+def trace_queue_stats(path: str, pattern: str):
+    """Per queue: (launches, average duration in us) of the kernels matching `pattern` in a rocprofv3
+    kernel-trace CSV (the stream a kernel was launched on maps to one queue)."""
+    import csv
+    import re
+
+    per = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if re.search(pattern, r["Kernel_Name"]):
+                d = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+                per.setdefault(int(r["Queue_Id"]), []).append(d)
+    return {q: (len(v), float(np.mean(v)) / 1e3) for q, v in sorted(per.items())}
+
+
 def summarize_trace(path: str, steps: int = 1, top: int = 25) -> str:
     """Per-kernel summary of a rocprofv3 kernel trace: the SQLite database that rocprofv3 writes by default
     (`*_results.db`, read through its `kernels` view) or a `*kernel_trace.csv`.  Kernels are grouped by
@@ -238,6 +253,61 @@ def summarize_trace(path: str, steps: int = 1, top: int = 25) -> str:
     for name, (n, t) in sorted(agg.items(), key=lambda kv: -kv[1][1])[:top]:
         lines.append(f"{100.0 * t / total:5.1f}% {t / 1e6 / steps:9.2f} {n / steps:13.1f} {t / n / 1e3:9.1f}  {name}")
     return "\n".join(lines)
+
+
+def counter_means(path: str, pattern: str):
+    """Per queue: (launches, mean, max) of the counter values (KiB per dispatch) that a rocprofv3 --pmc run
+    wrote to its *_counter_collection.csv, over the kernels whose name matches `pattern`."""
+    import csv
+    import re
+
+    per = {}
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            if re.search(pattern, r["Kernel_Name"]):
+                per.setdefault(int(r["Queue_Id"]), []).append(float(r["Counter_Value"]))
+    return {q: (len(v), float(np.mean(v)), float(np.max(v))) for q, v in sorted(per.items())}
+
+
+def traffic_report(family: str, workload: str, fetch_csv: str, write_csv: str, copy_fetch_csv: str,
+                   copy_write_csv: str, queue: int, algorithmic_bytes: float, commands: str) -> str:
+    """The text of profiles/<family>_traffic_<workload>.txt: FETCH_SIZE and WRITE_SIZE per dispatch of the
+    family's kernel (queue `queue`: the stream whose launches the roofline covers), each scaled by what the
+    counter reads for a plain 1 GiB device copy, beside the algorithmic bytes per launch and the SHA-256
+    of the kernel's sources (bench.py uses the traffic only while the sources are unchanged)."""
+    import hashlib
+
+    kern = {"lu_gemm": r"k_lu_gemm<", "dec_update": r"k_dec_update"}[family]
+    copy_bytes = float(1 << 30)
+    cf = counter_means(copy_fetch_csv, r"copyBuffer")
+    cw = counter_means(copy_write_csv, r"copyBuffer")
+    f_fetch = copy_bytes / (1024.0 * next(iter(cf.values()))[1])
+    f_write = copy_bytes / (1024.0 * next(iter(cw.values()))[1])
+    fm, wm = counter_means(fetch_csv, kern), counter_means(write_csv, kern)
+    rd = fm[queue][1] * 1024.0 * f_fetch
+    wr = wm[queue][1] * 1024.0 * f_write
+    h = hashlib.sha256()
+    for fsrc in TRAFFIC_SOURCES[family]:
+        with open(os.path.join(ROOT, fsrc), "rb") as fh:
+            h.update(fh.read())
+    lines = [f"HBM traffic of k_{family}, {workload} workload", "",
+             "commands (from the repository root, on one MI355X; one counter per run):", commands, "",
+             "report: python3 bench.py --traffic-report " + family + " ... (bench.traffic_report)",
+             f"copy calibration: FETCH_SIZE reads {1.0 / f_fetch:.4f} of the bytes a plain 1 GiB copy reads "
+             f"(factor {f_fetch:.4f}), WRITE_SIZE {1.0 / f_write:.4f} of the bytes written (factor {f_write:.4f})"]
+    for q in sorted(set(fm) | set(wm)):
+        n1, m1, x1 = fm.get(q, (0, 0.0, 0.0))
+        n2, m2, x2 = wm.get(q, (0, 0.0, 0.0))
+        lines.append(f"  queue {q}: {n1} launches; FETCH_SIZE mean {m1:.1f} KiB (max {x1:.1f}), "
+                     f"WRITE_SIZE mean {m2:.1f} KiB (max {x2:.1f})")
+    lines += ["", f"roofline queue: {queue}",
+              f"traffic_read_bytes_per_launch: {rd:.6e}",
+              f"traffic_write_bytes_per_launch: {wr:.6e}",
+              f"traffic_bytes_per_launch: {rd + wr:.6e}",
+              f"algorithmic_bytes_per_launch: {algorithmic_bytes:.6e}",
+              f"traffic_over_algorithmic: {(rd + wr) / algorithmic_bytes:.3f}",
+              f"kernel_source_sha256: {h.hexdigest()}"]
+    return "\n".join(lines) + "\n"
 
 
 def uneven_specs(n: int = UNEVEN["n"], seed: int = UNEVEN["seed"]):
@@ -811,6 +881,11 @@ def main():
                     help="only print a per-kernel summary of a rocprofv3 kernel trace (*_results.db or "
                          "*kernel_trace.csv) and exit (no GPU needed)")
     ap.add_argument("--trace-steps", type=int, default=1, help="--summarize-trace: steps the trace covers")
+    ap.add_argument("--traffic-report", nargs=8, default=None,
+                    metavar=("FAMILY", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "QUEUE",
+                             "ALG_BYTES", "COMMANDS"),
+                    help="only print the HBM-traffic summary of a kernel family from rocprofv3 counter CSVs "
+                         "(no GPU needed)")
     ap.add_argument("--spike-batch", type=int, default=0,
                     help="time Step 1 for this many instances with the plain recursion and through 2-16 SPIKE "
                          "partitions (small batches) and exit")
@@ -819,6 +894,14 @@ def main():
     args = ap.parse_args()
     if args.summarize_trace:
         print(summarize_trace(args.summarize_trace, args.trace_steps))
+        if not args.summarize_trace.endswith(".db"):
+            for name, pat in (("k_lu_gemm", r"k_lu_gemm<"), ("k_dec_update", r"k_dec_update")):
+                for q, (n, avg) in trace_queue_stats(args.summarize_trace, pat).items():
+                    print(f"# {name} on queue {q}: {n} launches, average {avg:.1f} us")
+        return
+    if args.traffic_report:
+        fam, fcsv, wcsv, cfcsv, cwcsv, q, alg, cmds = args.traffic_report
+        print(traffic_report(fam, args.workload, fcsv, wcsv, cfcsv, cwcsv, int(q), float(alg), cmds), end="")
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
