@@ -852,6 +852,46 @@ def run_spike(args):
     print(json.dumps(out))
 
 
+def compare_precisions(workload: str, steps: int = 1, warmup: int = 1):
+    """One timed step of `workload` in plain FP64 and in mixed precision (FP32 products in the block
+    formations and the chain, FP64 refinement of psi, T from the refined psi with the broadening tail),
+    each after `warmup` untimed steps: solves/s and T against the stored oracle values, so that every
+    default benchmark line carries the plain-FP64-versus-mixed comparison of the same configuration."""
+    import gc
+
+    import torch
+
+    res = {}
+    for mode in ("fp64", "mixed"):
+        print(f"{workload} {mode}: building the pipeline", file=sys.stderr, flush=True)
+        pipe = Pipeline(workload, mode=mode)
+        for _ in range(warmup):
+            pipe.run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            pipe.run()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        T = pipe.T.cpu().numpy() if mode == "fp64" else np.stack([pipe.T_psi.cpu().numpy()] * 2, axis=1)
+        rec = dict(solves_per_s=round(pipe.n * steps / dt, 3), ms_per_step=round(dt * 1e3 / steps, 1),
+                   instances=pipe.n, t_err_all=golden_errors(workload, T))
+        if mode != "fp64":
+            it = pipe.ir_iters.cpu().numpy()
+            rec.update(refine_iters=[int(it.min()), int(it.max())],
+                       refine_resid_max=float(pipe.ir_resid.max().item()), fp64_fallback=pipe.fallback)
+        res[mode] = rec
+        pipe.ctx.close()
+        pipe.ctx_s.close()
+        for k in list(vars(pipe)):
+            setattr(pipe, k, None)
+        del pipe
+        gc.collect()
+        torch.cuda.empty_cache()
+    res["config"] = dict(workload=workload, steps=steps, warmup=warmup)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -886,6 +926,9 @@ def main():
                              "ALG_BYTES", "COMMANDS"),
                     help="only print the HBM-traffic summary of a kernel family from rocprofv3 counter CSVs "
                          "(no GPU needed)")
+    ap.add_argument("--compare-precisions", action=argparse.BooleanOptionalAction, default=True,
+                    help="after the default dft512 line's step, time the s = 1024 workload once in plain FP64 "
+                         "and once in mixed precision and add both to the line (precision_comparison)")
     ap.add_argument("--spike-batch", type=int, default=0,
                     help="time Step 1 for this many instances with the plain recursion and through 2-16 SPIKE "
                          "partitions (small batches) and exit")
@@ -1039,6 +1082,20 @@ def main():
         "t_err_all": golden_errors(args.workload, T_np),
         "device_mem_used_gib": round((torch.cuda.mem_get_info()[1] - torch.cuda.mem_get_info()[0]) / 2**30, 1),
     }
+    if args.compare_precisions and args.workload == "dft512" and args.mode == "fp64":
+        # release this workload's device memory, then the s = 1024 workload in both precisions
+        pipe.ctx.close()
+        pipe.ctx_s.close()
+        for k in list(vars(pipe)):
+            setattr(pipe, k, None)
+        del pipe
+        import gc
+        gc.collect()
+        torch.cuda.empty_cache()
+        try:
+            out["precision_comparison"] = compare_precisions("dft1024")
+        except Exception as e:  # reported, never fatal for the headline line
+            out["precision_comparison"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out))
 
 
