@@ -7,7 +7,10 @@
   a non-retarded root (an exact fixed point) and poor starts are rejected and replaced by the decimation,
   whose result matches the oracle.
 * Training on self-energies of the decimation lowers the loss, and the trained network's prediction on
-  held-out (E, k) is closer to the decimation than the best prediction without it (the training mean).
+  held-out (E, k) is closer to the decimation than the best prediction without it (the training mean);
+  the warm-started results equal the oracle's decimation on a sample of those points.
+* At the learned workload's own lead size (s = 256) and network size: cold and warm self-energies
+  against the oracle, and the network's forward pass and gradients against the float64 oracle.
 """
 import numpy as np
 import pytest
@@ -203,3 +206,64 @@ def test_training_gains_over_the_mean_prediction(ctx):
     out = out.cpu().numpy()
     assert max(_rel(out[i], ref[i]) for i in range(n_test)) <= 1e-8
     print("accepted", int((info == 0).sum()), "of", n_test, flush=True)
+    # and the self-energies returned are the oracle's (decimation on the CPU) on a sample of the held-out points
+    for i in range(0, n_test, 16):
+        j = n_train + i
+        a0, a1, am1 = selfenergy.lead_blocks(*cells[j], E[j], ETA)
+        sl, sr, _, _ = selfenergy.decimation(a0, a1, am1)
+        tol = max(1e-10, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1))
+        assert _rel(out[i, 0], sl) <= tol and _rel(out[i, 1], sr) <= tol, (i, _rel(out[i, 0], sl), tol)
+
+
+def test_warm_start_at_the_learned_workload_size(ctx):
+    """The learned workload's lead (s = 256, the 4 x 8 x 8 slab of seed 4): cold decimation and the warm
+    start against the oracle's decimation; a start at the oracle's roots is accepted with no Newton step,
+    a start 1e-3 off is judged and either accepted or replaced, and the result is the oracle's either way.
+    The perceptron of that workload (35 -> 512 -> 512 -> 512 -> 4 s^2 = 262144 outputs, FP32) against the
+    float64 oracle on a few rows: outputs, loss and the gradients of every layer."""
+    import paper_1812_01396_amd as ss
+    s = 256
+    base = synth.DFTLikeCell(synth.SLAB_SHAPES[s], 4)
+    pts = [(-2.5, 0.4), (0.7, 1.9), (3.1, 2.8)]
+    cells = [base.at(k) for _, k in pts]
+    Es = np.array([e for e, _ in pts])
+    refs = []
+    for (E, _), cell in zip(pts, cells):
+        a0, a1, am1 = selfenergy.lead_blocks(*cell, E, ETA)
+        sl, sr, _, _ = selfenergy.decimation(a0, a1, am1)
+        refs.append((sl, sr, max(1e-10, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1))))
+    lead = _lead_tensors(cells)
+    Ed = torch.as_tensor(Es).cuda()
+    kidx = torch.arange(len(pts), dtype=torch.int32).cuda()
+    cold, _, _, info_c = ss.ss_lead_selfenergy(ctx, *lead, Ed, ETA, kidx=kidx)
+    exact = torch.as_tensor(np.stack([np.stack([sl, sr]) for sl, sr, _ in refs])).cuda()
+    rng = np.random.default_rng(8)
+    pert = exact.cpu().numpy() * (1 + 1e-3 * (rng.standard_normal(exact.shape) + 1j * rng.standard_normal(exact.shape)))
+    warm_x, itn_x, _, _, info_x = ss.ss_lead_selfenergy_warm(ctx, *lead, Ed, ETA, exact, kidx=kidx)
+    warm_p, _, _, _, info_p = ss.ss_lead_selfenergy_warm(ctx, *lead, Ed, ETA, torch.as_tensor(pert).cuda(),
+                                                        kidx=kidx)
+    torch.cuda.synchronize()
+    assert int((info_c != 0).sum()) == 0
+    assert info_x.cpu().tolist() == [0, 0, 0] and itn_x.cpu().tolist() == [0, 0, 0]
+    assert all(i in (0, -2) for i in info_p.cpu().tolist())
+    for out in (cold, warm_x, warm_p):
+        o = out.cpu().numpy()
+        for b, (sl, sr, tol) in enumerate(refs):
+            assert _rel(o[b, 0], sl) <= tol and _rel(o[b, 1], sr) <= tol, (b, _rel(o[b, 0], sl), tol)
+    # the network of that workload, on 6 rows
+    dims = [35, 512, 512, 512, 4 * s * s]
+    net = ss.MLP(ctx, dims, seed=2)
+    X = ss.ss_warm_features(ctx, torch.as_tensor(rng.uniform(-5, 5, 6)).cuda(),
+                            torch.as_tensor(rng.uniform(0, np.pi, 6)).cuda())
+    T = torch.as_tensor(rng.standard_normal((6, dims[-1])).astype(np.float32)).cuda()
+    acts, Y = net.forward(X)
+    loss = net.backward(X, acts, T)
+    torch.cuda.synchronize()
+    params = _unpack(net.params.cpu().numpy(), dims)
+    Xh = X.cpu().numpy().astype(np.float64)
+    ref_acts = warmstart.mlp_forward(params, Xh)
+    assert _rel(Y.cpu().numpy(), ref_acts[-1]) <= 1e-5
+    ref_loss, ref_grads = warmstart.mlp_loss_grad(params, Xh, T.cpu().numpy().astype(np.float64))
+    assert abs(float(loss.item()) - ref_loss) <= 1e-5 * ref_loss
+    for (gW, gb), (rW, rb) in zip(_unpack(net.grads.cpu().numpy(), dims), ref_grads):
+        assert _rel(gW, rW) <= 1e-4 and _rel(gb, rb) <= 1e-4
