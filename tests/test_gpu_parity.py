@@ -177,6 +177,8 @@ def test_obc_psi_transmission_vs_oracle(ctx, nb, s, m, absorb):
         assert _rel(out["psi"][b], ref["psi"]) <= tol
         for j, key in enumerate(("t_lr", "t_rl")):
             assert abs(out["T"][b, j] - ref[key]) <= tol * max(1.0, abs(ref[key]))
+            if absorb > 0:  # the benchmark's split meets the T target itself, whatever the tolerance allows
+                assert abs(out["T"][b, j] - ref[key]) <= 1e-8 * max(1.0, abs(ref[key])), (b, key, tol)
 
 
 @pytest.mark.parametrize("absorb", [0.0, 1.0])
