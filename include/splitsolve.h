@@ -82,6 +82,14 @@ const char *ss_status_string(ss_status st);
 const char *ss_last_error(const ss_ctx *ctx);
 /* Bytes of device workspace the context currently holds. */
 size_t ss_workspace_bytes(const ss_ctx *ctx);
+/* Bytes of device workspace a fresh context holds after one pass of the four steps in their order
+ * (ss_lead_selfenergy, ss_precompute_columns with `flags`, ss_apply_obc with m columns of psi,
+ * ss_transmission) for `batch` instances of nb blocks of size s, with the default LU panel widths; the
+ * same calls with these sizes or smaller then run without growing any workspace (for instance in
+ * sync-free mode, under stream capture).  Refinement, plans, SPIKE partitions and the warm start need
+ * more.  prec is accepted for completeness (the products' precision does not change the workspace).
+ * SS_ERR_ARG for sizes out of range or a NULL `bytes`. */
+ss_status ss_workspace_size(int batch, int nb, int s, int m, int prec, int flags, size_t *bytes);
 
 /* Kernel timing probe (a profiling aid).  ss_kernel_timer(ctx, family) waits for the stream, clears
  * the accumulated time and from then on brackets every launch of that kernel family on this context

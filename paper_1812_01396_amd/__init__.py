@@ -32,4 +32,5 @@ from .splitsolve import (  # noqa: F401
     ss_transmission,
     ss_transmission_noalloc,
     ss_transmission_psi,
+    ss_workspace_size,
 )

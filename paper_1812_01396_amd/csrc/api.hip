@@ -177,6 +177,60 @@ size_t ss_workspace_bytes(const ss_ctx *ctx) {
   return t;
 }
 
+namespace {
+// One workspace request in call order, as workspace() grants it: grow-only, 9/8 of the request.
+void ws_request(size_t *hold, Slot slot, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  if (hold[slot] < bytes) hold[slot] = bytes + bytes / 8;
+}
+// Inverses of the diagonal blocks that a batched LU of order n keeps for its triangular leaves.
+size_t lu_inverse_bytes(size_t nmat, int n) {
+  const size_t w = (size_t)lu_panel_width(n);
+  return sizeof(double2) * nmat * (size_t)cdiv(n, (int)w) * 2 * w * w;
+}
+}  // namespace
+
+ss_status ss_workspace_size(int batch, int nb, int s, int m, int prec, int flags, size_t *bytes) {
+  if (!bytes || batch < 0 || nb < 1 || s < 1 || m < 0) return SS_ERR_ARG;
+  if (s > SS_MAX_S) return SS_ERR_UNSUPPORTED;
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU) return SS_ERR_ARG;
+  // the requests of the four steps in their order, mirroring the drivers (the decimation, the
+  // recursion's sweep, the corner system, the transmission); the precision does not change them
+  size_t h[kNumSlots] = {};
+  const size_t c = sizeof(double2), i4 = sizeof(int), b = (size_t)batch, S = (size_t)s, ss2 = S * S;
+  // ss_lead_selfenergy: decimation state and systems, then the final solves
+  ws_request(h, kSlotDec, c * 12 * ss2 * b);
+  ws_request(h, kSlotPerm, i4 * 2 * b * S);
+  ws_request(h, kSlotZp, i4 * 2 * b);
+  ws_request(h, kSlotMisc, b * (2 * 8 + 8 + 4 + 4 + 4) + 64 + b * 4 * 8);
+  ws_request(h, kSlotLuInv, lu_inverse_bytes(b, s));
+  ws_request(h, kSlotObc, c * 2 * b * ss2);
+  ws_request(h, kSlotLuInv, lu_inverse_bytes(2 * b, s));
+  // ss_precompute_columns: the augmented systems of both recursions and their solution slots
+  ws_request(h, kSlotM, c * 2 * b * S * 2 * S);
+  ws_request(h, kSlotPerm, i4 * 2 * b * S);
+  ws_request(h, kSlotZp, i4 * 3 * b);
+  ws_request(h, kSlotX, c * 2 * b * (size_t)nb * ss2);
+  if (flags & SS_KEEP_FACTORS) {
+    ws_request(h, kSlotFact, c * b * (size_t)nb * ss2);
+    ws_request(h, kSlotFactPerm, i4 * b * (size_t)nb * S);
+  }
+  ws_request(h, kSlotLuInv, lu_inverse_bytes(2 * b, s));
+  // ss_apply_obc: the corner systems [R | C Q b' | I] of order 2s
+  const size_t n = 2 * S, nrhs = 2 * S + (size_t)m, ldm = 4 * S + (size_t)m;
+  ws_request(h, kSlotM, c * b * n * ldm);
+  ws_request(h, kSlotPerm, i4 * b * n);
+  ws_request(h, kSlotZp, i4 * b);
+  ws_request(h, kSlotObc, c * b * (4 * ss2 + n * nrhs));
+  ws_request(h, kSlotLuInv, lu_inverse_bytes(b, 2 * s));
+  // ss_transmission: per-tile partial sums
+  ws_request(h, kSlotMisc, sizeof(double) * transmission_partials(batch, s));
+  size_t t = 0;
+  for (int k = 0; k < kNumSlots; ++k) t += h[k];
+  *bytes = batch == 0 ? 0 : t;
+  return SS_OK;
+}
+
 ss_status ss_kernel_timer(ss_ctx *ctx, const char *family) {
   SS_TRY(enter(ctx));
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");

@@ -23,7 +23,7 @@ SS_KEEP_FACTORS = 1
 
 EXPORTS = (
     "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_set_lu_width", "ss_synchronize", "ss_status_string", "ss_last_error",
-    "ss_workspace_bytes", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
+    "ss_workspace_bytes", "ss_workspace_size", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_transmission_noalloc",
     "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
@@ -97,6 +97,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_last_error.restype = ctypes.c_char_p
     lib.ss_workspace_bytes.argtypes = [P]
     lib.ss_workspace_bytes.restype = Z
+    lib.ss_workspace_size.argtypes = [I, I, I, I, I, I, ctypes.POINTER(Z)]
+    lib.ss_workspace_size.restype = I
     lib.ss_measure_ceilings.argtypes = [P, ctypes.POINTER(D)]
     lib.ss_measure_ceilings.restype = I
     lib.ss_kernel_timer.argtypes = [P, ctypes.c_char_p]
@@ -712,3 +714,14 @@ def ss_precompute_columns_spike(ctx: Context, Hd, Hu, Sd, Su, E, nparts: int, ki
     ctx.check(ctx.lib.ss_precompute_columns_spike(ctx.handle, ctypes.byref(btd), batch, _ptr(kidx), _ptr(E),
                                                   float(absorb), int(prec), int(nparts), _ptr(Q), _ptr(info)))
     return Q, info
+
+
+def ss_workspace_size(batch: int, nb: int, s: int, m: int = 0, prec: int = SS_PREC_FP64, flags: int = 0) -> int:
+    """Device workspace a fresh context holds after one pass of the four steps at these sizes (see
+    ss_workspace_size in splitsolve.h).  Host-only: needs the library, not a GPU."""
+    lib = load_library()
+    out = ctypes.c_size_t()
+    st = lib.ss_workspace_size(int(batch), int(nb), int(s), int(m), int(prec), int(flags), ctypes.byref(out))
+    if st != SS_OK:
+        raise SplitSolveError(st, "ss_workspace_size: argument out of range")
+    return int(out.value)

@@ -82,3 +82,18 @@ def test_binding_validates_tensors():
         splitsolve._need(y, torch.complex128, dev, "y")  # wrong device
     with pytest.raises(ValueError):
         splitsolve._check_kidx(torch.tensor([0, 3], dtype=torch.int32), 2)
+
+
+def test_workspace_size_query_host_side(lib):
+    """ss_workspace_size needs no GPU: it grows with the batch and the block count, is zero for an empty
+    batch, and rejects sizes out of range."""
+    from paper_1812_01396_amd import splitsolve
+    q = splitsolve.ss_workspace_size
+    assert q(0, 4, 16) == 0
+    assert 0 < q(2, 4, 16, 3) < q(4, 4, 16, 3) < q(4, 9, 16, 3)
+    assert q(4, 9, 16, 3, flags=splitsolve.SS_KEEP_FACTORS) > q(4, 9, 16, 3)
+    for bad in [(-1, 4, 16), (2, 0, 16), (2, 4, 0)]:
+        with pytest.raises(splitsolve.SplitSolveError):
+            q(*bad)
+    with pytest.raises(splitsolve.SplitSolveError):
+        q(2, 4, 2048)

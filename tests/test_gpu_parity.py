@@ -263,3 +263,26 @@ def test_lu_factor_zero_pivots(ctx):
         assert np.array_equal(perm.cpu().numpy()[b], rperm)
         assert np.abs(lu.cpu().numpy()[b] - ref).max() <= 1e-11 * np.abs(ref).max()
     assert list(info.cpu().numpy()) == [18, 40]
+
+
+@pytest.mark.parametrize("batch,nb,s,m,keep", [(3, 4, 40, 3, False), (2, 3, 130, 5, True), (1, 1, 16, 0, False)])
+def test_workspace_size_matches_a_fresh_context(batch, nb, s, m, keep):
+    """ss_workspace_size equals what a fresh context holds after one pass of the four steps."""
+    import paper_1812_01396_amd as ss
+    c = ss.Context(0)
+    try:
+        insts = [synth.random_btd(nb, s, seed=3300 + k) for k in range(batch)]
+        hd, hu, sd, su = (_dev(np.stack([getattr(i, f) for i in insts])) for f in ("Hd", "Hu", "Sd", "Su"))
+        leads = [_dev(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01")]
+        E = _dev(np.linspace(-0.4, 0.4, batch), torch.float64)
+        kidx = torch.arange(batch, dtype=torch.int32, device="cuda")
+        sig, _, _, _ = ss.ss_lead_selfenergy(c, *leads, E, 1e-8, kidx=kidx)
+        q, _ = ss.ss_precompute_columns(c, hd, hu, sd, su, E, kidx=kidx, keep_factors=keep, absorb=1.0)
+        inj = _dev(np.stack([synth.injection_block(s, m, 5 + b) for b in range(batch)])) if m else None
+        _, gc, _ = ss.ss_apply_obc(c, q, sig, inj=inj, absorb=1.0)
+        ss.ss_transmission(c, gc, sig)
+        torch.cuda.synchronize()
+        flags = ss.splitsolve.SS_KEEP_FACTORS if keep else 0
+        assert c.workspace_bytes() == ss.ss_workspace_size(batch, nb, s, m, flags=flags)
+    finally:
+        c.close()
