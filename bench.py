@@ -605,7 +605,7 @@ class Pipeline:
     """
 
     def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-12,
-                 accept_tol: float = 1e-10, absorb: float | None = None):
+                 accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0):
         import torch
 
         import paper_1812_01396_amd as ss
@@ -620,6 +620,8 @@ class Pipeline:
         w = dict(w)
         if absorb is not None:
             w["absorb"] = absorb
+        if m > 0 and mode != "fp64":  # columns of the injection factor W_L (the seeded b' of FP64 mode keeps its m)
+            w["m"] = m
         self.absorb = w["absorb"]
         self.w, self.insts, self.E_np, self.kidx_np, self.inj_np = w, insts, E_np, kidx_np, inj_np
         s, nb, m = w["s"], w["nb"], w["m"]
@@ -637,7 +639,8 @@ class Pipeline:
         self.lead = [t(np.stack([getattr(i, f) for i in insts])) for f in ("H00", "H01", "S00", "S01")]
         self.E = t(E_np, torch.float64)
         self.kidx = t(kidx_np, torch.int32)
-        self.inj = t(inj_np)
+        # FP64 mode injects the seeded b'; the mixed modes write W_L of their own width here
+        self.inj = t(inj_np) if mode == "fp64" else torch.zeros(nb_inst, 2 * s, m, dtype=torch.complex128, device=dev)
         c128 = torch.complex128
         self.sigma = torch.empty(nb_inst, 2, s, s, dtype=c128, device=dev)
         self.iters = torch.empty(nb_inst, dtype=torch.int32, device=dev)
@@ -908,6 +911,8 @@ def main():
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
+    ap.add_argument("--refine-tol", type=float, default=1e-12, help="mixed: relative residual the refinement stops at")
+    ap.add_argument("--m-inj", type=int, default=0, help="mixed: columns of the injection factor (0: workload's m)")
     ap.add_argument("--roofline-kernel", default="lu_gemm",
                     help="kernel family timed with HIP events for the roofline entry")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -976,7 +981,8 @@ def main():
         return run_uneven(args)
     if args.workload == "learned":
         return run_learned(args)
-    pipe = Pipeline(args.workload, args.chunk, args.mode, absorb=None if args.absorb < 0 else args.absorb)
+    pipe = Pipeline(args.workload, args.chunk, args.mode, absorb=None if args.absorb < 0 else args.absorb,
+                    refine_tol=args.refine_tol, m=args.m_inj)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel
     timed_ctx = pipe.ctx_s if fam in ("dec_update",) else pipe.ctx

@@ -930,6 +930,73 @@ __global__ void k_copy_out(LuArgs a) {
   }
 }
 
+// ------------------------------------------------------------------ narrow solves with kept factors
+//
+// The refinement applies kept factors to a few right-hand-side columns (m, typically 32).  The recursive
+// solve would issue about two launches per 32 rows and triangle, each far too small to fill the chip.
+// Here a diagonal block of up to kTrsmBlock rows is solved by ONE launch: a workgroup owns one system
+// and NarrowTile::BN columns and walks the block in panels of 32 rows (the rows of the right-hand sides
+// minus the product with the block's already solved rows, a matrix-core product whose depth grows with
+// the panel, then the 32 x 32 triangle by substitution, in place); the products between blocks are the
+// factorization's own batched products, so a triangle of order n takes n / kTrsmBlock block launches and
+// one fewer products.
+using NarrowTile = TileCfg<32, 32, 32, 2, 2>;
+constexpr int kTrsmBlock = 256;
+
+template <bool kUpper>
+__global__ void __launch_bounds__(NarrowTile::NT) k_trsm_block(LuArgs a, int r0, int rows, int c_lo, int c_hi) {
+  using T = NarrowTile;
+  constexpr int P = 32;   // panel rows
+  constexpr int CP = 33;  // LDS pitch of the staged right-hand sides (32 columns)
+  __shared__ double lds[T::LDS_DOUBLES];
+  __shared__ double cr[P * CP], ci[P * CP];
+  __shared__ double2 tri[P][P + 1];
+  __shared__ double2 rdiag[P];
+  __shared__ int sperm[kTrsmBlock];
+  const int mat = blockIdx.y;
+  if (skipped(a, mat)) return;
+  const int n = a.n, rb = min(rows, n - r0);
+  const int c0 = c_lo + blockIdx.x * T::BN, cw = min(T::BN, c_hi - c0);
+  double2 *M = a.M + (long)mat * a.sM;
+  const ColView cv = col_view(a, mat, c_lo);  // right-hand sides: element (physical row, column c >= n)
+  const int *perm = a.perm + (long)mat * a.sP;
+  for (int i = threadIdx.x; i < rb; i += T::NT) sperm[i] = perm[r0 + i];  // block-local rows
+  __syncthreads();
+  const int npanel = cdiv(rb, P);
+  // operands in block-local coordinates: the factor's rows r0 + r, columns r0 + k; the right-hand sides'
+  // rows r0 + k (physical through the row map), columns c0 + c
+  LdRowPerm la{M + r0, a.ldm, sperm};
+  LdRowPerm lb{cv.p + c0, cv.ld, sperm};
+  for (int q = 0; q < npanel; ++q) {
+    const int pidx = kUpper ? npanel - 1 - q : q;
+    const int p0 = pidx * P, w = min(P, rb - p0);
+    Acc<T> acc;
+    acc.zero();
+    if (kUpper) mma_loop<T>(la, lb, p0, rb, 0, cw, p0 + P, rb, acc, lds);  // U[panel][p0+P : rb] X
+    else mma_loop<T>(la, lb, p0, rb, 0, cw, 0, p0, acc, lds);              // L[panel][0 : p0] Y
+    acc_foreach<T>(acc, [&](int r, int c, double2 v) {
+      double2 b = make_double2(0.0, 0.0);
+      if (r < w && c < cw) b = csub(cv.p[(long)sperm[p0 + r] * cv.ld + c0 + c], v);
+      cr[r * CP + c] = b.x;
+      ci[r * CP + c] = b.y;
+    });
+    for (int idx = threadIdx.x; idx < P * P; idx += T::NT) {
+      const int i = idx / P, j = idx % P;
+      const bool in = i < w && j < w && (kUpper ? j > i : j < i);
+      st2(tri[i][j], in ? M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + j] : make_double2(0.0, 0.0));
+      if (kUpper && j == i)
+        st2(rdiag[i], i < w ? crecip(M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + i]) : make_double2(0.0, 0.0));
+    }
+    __syncthreads();
+    tile_trsm<P, kUpper>(
+        [&](int i, int col) { return col < P ? make_double2(cr[i * CP + col], ci[i * CP + col]) : make_double2(0.0, 0.0); },
+        tri, rdiag, w, [&](int i, int col, double2 x) {
+          if (col < cw) cv.p[(long)sperm[p0 + i] * cv.ld + c0 + col] = x;
+        });
+    __syncthreads();  // the panel's rows are stored before the next panel's product reads them
+  }
+}
+
 // ------------------------------------------------------------------ driver
 
 template <int W, int R, int LB>
@@ -1064,6 +1131,36 @@ struct LuRun {
     gemm(cm, d.n, cm, c1, c0, cm);
     factor(cm, c1);
   }
+  // the two triangles for a few right-hand-side columns: blocks of kTrsmBlock rows by k_trsm_block,
+  // the products between blocks by gemm, then the solution rows to X in natural order
+  void narrow(bool upper, int lo, int hi) {
+    const int c_lo = d.n, c_hi = d.n + d.nrhs;
+    if (hi - lo <= kTrsmBlock) {
+      const dim3 grid(cdiv(c_hi - c_lo, NarrowTile::BN), d.nmat);
+      KernelScope ks_(ctx, "trsm");
+      if (upper) hipLaunchKernelGGL(k_trsm_block<true>, grid, dim3(NarrowTile::NT), 0, ctx->stream, a, lo, hi - lo, c_lo, c_hi);
+      else hipLaunchKernelGGL(k_trsm_block<false>, grid, dim3(NarrowTile::NT), 0, ctx->stream, a, lo, hi - lo, c_lo, c_hi);
+      return;
+    }
+    const int m = lo + std::max(kTrsmBlock, ((hi - lo) / 2 + kTrsmBlock - 1) / kTrsmBlock * kTrsmBlock);
+    if (!upper) {
+      narrow(false, lo, m);
+      gemm(m, hi, c_lo, c_hi, lo, m);
+      narrow(false, m, hi);
+    } else {
+      narrow(true, m, hi);
+      gemm(lo, m, c_lo, c_hi, m, hi);
+      narrow(true, lo, m);
+    }
+  }
+  ss_status apply_narrow() {
+    narrow(false, 0, d.n);
+    narrow(true, 0, d.n);
+    const long total = (long)d.n * d.nrhs;
+    const int blocks = (int)std::min<long>((total + 255) / 256, 256);
+    hipLaunchKernelGGL(k_copy_out, dim3(blocks, d.nmat), dim3(256), 0, ctx->stream, a);
+    return check_launch(ctx, "lu_apply");
+  }
   ss_status run(bool do_factor = true) {
     if (do_factor) factor(0, d.n);
     if (d.nrhs > 0) {
@@ -1100,6 +1197,11 @@ ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_apply: order out of range");
   const int W = panel_width(ctx, d.n);
+  if (d.nrhs <= 2 * NarrowTile::BN) {  // a few columns: diagonal blocks of kTrsmBlock rows, one launch each
+    if (W == 32) return LuRun<32, 1, 1024>{ctx, d, make_args(d)}.apply_narrow();
+    if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.apply_narrow();
+    return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.apply_narrow();
+  }
   if (W == 32) return LuRun<32, 1, 1024>{ctx, d, make_args(d)}.run(false);
   if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.run(false);
   return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.run(false);
