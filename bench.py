@@ -452,6 +452,7 @@ def run_uneven(args):
                          frac=round(achieved / FP64_PEAK_TFLOPS, 4), traffic=None, kernel="whole step"),
         "plan_create_s": round(pipe.create_s, 2),
         "graph_nodes": pipe.plan.graph_nodes,
+        "graph_segments": pipe.plan.graph_segments,
         "groups": groups,
         "decimation_iters": [int(info[:, 3].min()), int(info[:, 3].max())],
         "nonzero_info": int((info[:, :3] != 0).sum()),

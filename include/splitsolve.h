@@ -368,8 +368,9 @@ ss_status ss_lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const s
  * group by nb and splits it into chunks that fit `mem_bytes`; a chunk runs the whole hot path
  * (self-energies, Step 1, Steps 2-4, Caroli T) in lockstep, launching at recursion step t only the
  * instances with more than t blocks.  Groups run on streams of their own.  With use_graph each group's
- * work is captured once into a graph at creation and every ss_plan_execute is one graph launch per
- * group (on the group's stream, all forked from and joined into one origin stream).
+ * work is captured once at creation, as a sequence of graph segments of about graph_segment_nodes
+ * nodes each (cut at launch sites), and every ss_plan_execute replays each group's segments in order on
+ * the group's stream (all groups forked from and joined into one origin stream).
  * With autotune, candidate LU panel widths and chunk sizes are timed per group at creation.
  *
  * Instance blocks are device pointers owned by the caller and must stay valid and unmoved for the
@@ -396,6 +397,7 @@ typedef struct {
   int use_graph;     /* nonzero: capture each size group's work into a graph at creation */
   int autotune;      /* nonzero: time candidate panel widths and chunk sizes per group at creation */
   size_t mem_bytes;  /* device memory for chunk work (0: 32 GiB); a chunk always holds one instance */
+  int graph_segment_nodes; /* with use_graph: nodes per captured graph segment (0: 2048; at most 4096) */
 } ss_plan_opts;
 
 typedef struct ss_plan ss_plan;
@@ -415,9 +417,11 @@ int ss_plan_groups(const ss_plan *plan);
 ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, int *chunk, int *lu_width,
                            double *tune_ms);
 /* Nodes of the captured group graphs, summed (0 without use_graph); a negative value -n means that a
- * group graph came out larger than 8192 nodes (n summed over the groups), and the plan runs as one
+ * graph segment came out larger than 8192 nodes (n summed over the groups), and the plan runs as one
  * sync-free enqueue of the same launches instead. */
 long long ss_plan_graph_nodes(const ss_plan *plan);
+/* Captured graph segments, summed over the groups (0 when the plan does not replay graphs). */
+int ss_plan_graph_segments(const ss_plan *plan);
 /* Waits for the plan's work and frees it (it does not use the context: a plan may outlive it). */
 void ss_plan_destroy(ss_plan *plan);
 

@@ -64,7 +64,28 @@ static hipEvent_t timer_event(ss_ctx *ctx) {
   return ctx->timer_events[ctx->timer_used++];
 }
 
+void segment_point(ss_ctx *ctx) {
+  if (!ctx->seg_graphs || ctx->seg_failed) return;
+  hipStreamCaptureStatus status = hipStreamCaptureStatusNone;
+  hipGraph_t cur = nullptr;
+  size_t nodes = 0;
+  if (hipStreamGetCaptureInfo_v2(ctx->stream, &status, nullptr, &cur, nullptr, nullptr) != hipSuccess ||
+      status != hipStreamCaptureStatusActive || !cur || hipGraphGetNodes(cur, nullptr, &nodes) != hipSuccess) {
+    ctx->seg_failed = true;
+    return;
+  }
+  if (nodes < ctx->seg_limit) return;
+  hipGraph_t done = nullptr;
+  if (hipStreamEndCapture(ctx->stream, &done) != hipSuccess || !done) {
+    ctx->seg_failed = true;
+    return;
+  }
+  ctx->seg_graphs->push_back(done);
+  if (hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) ctx->seg_failed = true;
+}
+
 KernelScope::KernelScope(ss_ctx *c, const char *family, double flops, double bytes) : ctx(c), on(false) {
+  segment_point(ctx);
   const std::string &tf = ctx->timer_family;
   const bool match = !tf.empty() && (tf == family || (tf[0] == ',' && tf.find(std::string(",") + family + ",") !=
                                                                            std::string::npos));

@@ -114,6 +114,12 @@ struct ss_ctx {
   size_t timer_used = 0;
   double timer_flops = 0.0;  // algorithmic flops of the timed launches (where the launch site states them)
   double timer_bytes = 0.0;  // algorithmic HBM bytes of the same launches (operands read once, results written once)
+  // graph segments: while seg_graphs is set and the stream is being captured, a capture that has grown
+  // to seg_limit nodes is closed at the next launch site (into seg_graphs) and a new one begun on the
+  // same stream, so no captured graph grows past about seg_limit nodes
+  std::vector<hipGraph_t> *seg_graphs = nullptr;
+  size_t seg_limit = 0;
+  bool seg_failed = false;  // closing or reopening a capture failed (the capture is then broken)
 };
 
 namespace ss {
@@ -123,6 +129,10 @@ ss_status workspace(ss_ctx *ctx, Slot s, size_t bytes, void **out);
 ss_status fail(ss_ctx *ctx, ss_status st, const std::string &msg);
 ss_status check_launch(ss_ctx *ctx, const char *what);
 ss_status host_word(ss_ctx *ctx, int **out);
+
+// A launch site: while the context's stream is captured in segments, starts a new graph segment once
+// the current one holds seg_limit nodes (every launch scope passes here before its launches).
+void segment_point(ss_ctx *ctx);
 
 // Brackets the launches issued in its scope with a pair of events when `family` is being timed.
 struct KernelScope {

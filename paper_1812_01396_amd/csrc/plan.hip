@@ -47,8 +47,9 @@ struct Group {
   ss_c128 *Q = nullptr, *sigma = nullptr, *inj = nullptr, *gc = nullptr;
   double *T = nullptr;
   int *info = nullptr;  // [4][chunk]
-  hipGraph_t graph = nullptr;  // the group's captured work (when the plan uses graphs)
-  hipGraphExec_t exec = nullptr;
+  // the group's captured work (when the plan uses graphs): segments replayed in order on its stream
+  std::vector<hipGraph_t> graphs;
+  std::vector<hipGraphExec_t> execs;
   size_t nodes = 0;
 };
 
@@ -64,10 +65,13 @@ __global__ void k_plan_scatter(const double *Tc, const int *ic, const int *orig,
 
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Largest captured group graph that is instantiated; a plan with a larger one runs as a sync-free
-// enqueue of the same launches.  Instantiating captured graphs of about 10^5 kernel nodes (long single
-// dependency chains) ended the host process with a segmentation fault in this runtime, while graphs of
-// a few thousand nodes replay correctly; the bound keeps instantiation to the range that was exercised.
+// A group's work is captured as a sequence of graphs of at most about kGraphSegmentNodes nodes each
+// (ss_plan_opts::graph_segment_nodes), replayed in order on the group's stream.  Instantiating captured
+// graphs of about 10^4 to 10^5 kernel nodes (long single dependency chains) ended the host process with
+// a segmentation fault in this runtime, while graphs of a few thousand nodes replay correctly; segments
+// keep every instantiated graph in that range.  A segment above kMaxGraphNodes (a segment grows by at
+// most one launch scope past its limit) makes the plan fall back to a sync-free enqueue.
+constexpr size_t kGraphSegmentNodes = 2048;
 constexpr size_t kMaxGraphNodes = 8192;
 
 }  // namespace
@@ -83,9 +87,10 @@ struct ss_plan {
   std::vector<Group> groups;
   hipEvent_t start = nullptr, finish = nullptr;
   hipStream_t origin = nullptr;  // the stream the batch forks from (captured when a graph is built)
-  bool graphs = false;           // every group replays its own captured graph
+  bool graphs = false;           // every group replays its own captured graph segments
   size_t graph_nodes = 0;       // summed over the groups
-  long long graph_refused = 0;  // nodes of a captured group graph judged too large to instantiate
+  size_t graph_segments = 0;    // summed over the groups
+  long long graph_refused = 0;  // nodes of a capture with a segment judged too large to instantiate
 };
 
 namespace {
@@ -238,21 +243,30 @@ ss_status run_group(ss_plan *p, Group &g) {
   return st == SS_OK ? SS_OK : fail(p->ctx, st, msg);
 }
 
-// Enqueue the whole batch on `origin`: every group forks from it and joins back into it.  With graphs,
-// each group's work is one launch of its captured graph on its stream.  Without, each group enqueues
-// its launches from a host thread of its own: a launch blocks the enqueuing thread while the stream's
-// hardware queue is full, so one thread enqueuing group after group would keep every group but the
-// current one idle (the groups would run one after the other).
+// Launch a group's captured graph segments in order on its stream.
+ss_status launch_group(Group &g, std::string &msg) {
+  for (hipGraphExec_t e : g.execs)
+    if (hipGraphLaunch(e, g.stream) != hipSuccess) {
+      msg = "group s=" + std::to_string(g.s) + ": graph launch failed";
+      return SS_ERR_DEVICE;
+    }
+  return SS_OK;
+}
+
+// Enqueue the whole batch on `origin`: every group forks from it and joins back into it.  Each group
+// enqueues from a host thread of its own, its captured graph segments (with graphs) or its launches: a
+// launch blocks the enqueuing thread while the stream's hardware queue is full, so one thread
+// enqueuing group after group would keep every group but the current one idle (the groups would run
+// one after the other).
 ss_status enqueue(ss_plan *p, hipStream_t origin) {
   if (hipEventRecord(p->start, origin) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: event record failed");
   for (Group &g : p->groups)
     if (hipStreamWaitEvent(g.stream, p->start, 0) != hipSuccess)
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: stream wait failed");
-  if (p->graphs) {
-    for (Group &g : p->groups)
-      if (hipGraphLaunch(g.exec, g.stream) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: graph launch failed");
-  } else if (p->groups.size() == 1) {
-    SS_TRY(run_group(p, p->groups[0]));
+  if (p->groups.size() == 1) {
+    std::string msg;
+    const ss_status st = p->graphs ? launch_group(p->groups[0], msg) : enqueue_group(p, p->groups[0], msg);
+    if (st != SS_OK) return fail(p->ctx, st, msg);
   } else {
     const size_t ng = p->groups.size();
     std::vector<ss_status> st(ng, SS_OK);
@@ -266,7 +280,7 @@ ss_status enqueue(ss_plan *p, hipStream_t origin) {
           msg[i] = "hipSetDevice failed in an enqueue thread";
           return;
         }
-        st[i] = enqueue_group(p, p->groups[i], msg[i]);
+        st[i] = p->graphs ? launch_group(p->groups[i], msg[i]) : enqueue_group(p, p->groups[i], msg[i]);
       });
     for (std::thread &t : th) t.join();
     for (size_t i = 0; i < ng; ++i)
@@ -278,38 +292,69 @@ ss_status enqueue(ss_plan *p, hipStream_t origin) {
   return SS_OK;
 }
 
-// Capture every group's work into a graph of its own (capture on the group's stream).  A group whose
-// graph exceeds kMaxGraphNodes makes the plan fall back to the sync-free enqueue for all groups.
+// Capture every group's work (capture on the group's stream) into graph segments of about
+// graph_segment_nodes nodes each: the group's context closes the current capture at a launch site once
+// it holds that many nodes and opens the next.  A segment above kMaxGraphNodes makes the plan fall back
+// to the sync-free enqueue for all groups.
 ss_status capture_groups(ss_plan *p) {
-  size_t total = 0;
+  size_t total = 0, nseg = 0;
   bool too_big = false;
+  const size_t limit = p->opts.graph_segment_nodes > 0 ? (size_t)p->opts.graph_segment_nodes : kGraphSegmentNodes;
+  auto drop = [&]() {
+    for (Group &g : p->groups) {
+      for (hipGraph_t gr : g.graphs) (void)hipGraphDestroy(gr);
+      g.graphs.clear();
+      g.nodes = 0;
+    }
+  };
   for (Group &g : p->groups) {
-    if (hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    if (hipStreamBeginCapture(g.stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      drop();
       return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: stream capture could not start");
+    }
+    g.ctx->seg_graphs = &g.graphs;
+    g.ctx->seg_limit = limit;
+    g.ctx->seg_failed = false;
     const ss_status st = run_group(p, g);
-    hipGraph_t graph = nullptr;
-    const hipError_t ec = hipStreamEndCapture(g.stream, &graph);
-    g.graph = graph;
-    if (st != SS_OK) return st;
-    if (ec != hipSuccess || !graph) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: capture failed");
-    if (hipGraphGetNodes(g.graph, nullptr, &g.nodes) != hipSuccess)
-      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph node count failed");
+    g.ctx->seg_graphs = nullptr;
+    hipGraph_t last = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g.stream, &last);
+    if (last) g.graphs.push_back(last);
+    if (st != SS_OK) {
+      drop();
+      return st;
+    }
+    if (g.ctx->seg_failed || ec != hipSuccess || !last) {
+      drop();
+      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: capture failed");
+    }
+    for (hipGraph_t gr : g.graphs) {
+      size_t n = 0;
+      if (hipGraphGetNodes(gr, nullptr, &n) != hipSuccess) {
+        drop();
+        return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph node count failed");
+      }
+      g.nodes += n;
+      if (n > kMaxGraphNodes) too_big = true;
+    }
     total += g.nodes;
-    if (g.nodes > kMaxGraphNodes) too_big = true;
+    nseg += g.graphs.size();
   }
   if (too_big) {
     p->graph_refused = (long long)total;
-    for (Group &g : p->groups) {
-      (void)hipGraphDestroy(g.graph);
-      g.graph = nullptr;
-    }
+    drop();
     return SS_OK;
   }
   for (Group &g : p->groups)
-    if (hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0) != hipSuccess)
-      return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed");
+    for (hipGraph_t gr : g.graphs) {
+      hipGraphExec_t e = nullptr;
+      if (hipGraphInstantiate(&e, gr, nullptr, nullptr, 0) != hipSuccess || !e)
+        return fail(p->ctx, SS_ERR_DEVICE, "ss_plan_create: graph instantiation failed");
+      g.execs.push_back(e);
+    }
   p->graphs = true;
   p->graph_nodes = total;
+  p->graph_segments = nseg;
   return SS_OK;
 }
 
@@ -363,8 +408,8 @@ void release(ss_plan *p) {
   if (p->origin) (void)hipStreamSynchronize(p->origin);
   for (Group &g : p->groups) {
     if (g.stream) (void)hipStreamSynchronize(g.stream);
-    if (g.exec) (void)hipGraphExecDestroy(g.exec);
-    if (g.graph) (void)hipGraphDestroy(g.graph);
+    for (hipGraphExec_t e : g.execs) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t gr : g.graphs) (void)hipGraphDestroy(gr);
     if (g.ctx) ss_destroy(g.ctx);
     if (g.tables) (void)hipFree(g.tables);
     if (g.work) (void)hipFree(g.work);
@@ -389,7 +434,8 @@ ss_status ss_plan_create(ss_ctx *ctx, int n, const ss_instance *inst, const ss_p
   if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "hipSetDevice failed");
   if (n < 1 || !inst || !opts || !T || !info) return fail(ctx, SS_ERR_ARG, "ss_plan_create: null argument or n < 1");
   if (opts->m < 0 || opts->m > SS_MAX_S || opts->eta < 0 || !(opts->absorb >= 0) || !std::isfinite(opts->absorb) ||
-      opts->sigma_tol < 0 || opts->sigma_passes < 0)
+      opts->sigma_tol < 0 || opts->sigma_passes < 0 || opts->graph_segment_nodes < 0 ||
+      opts->graph_segment_nodes > (int)kGraphSegmentNodes * 2)
     return fail(ctx, SS_ERR_ARG, "ss_plan_create: option out of range");
   for (int i = 0; i < n; ++i) {
     const ss_instance &in = inst[i];
@@ -520,6 +566,8 @@ long long ss_plan_graph_nodes(const ss_plan *p) {
   if (!p) return 0;
   return p->graph_nodes ? (long long)p->graph_nodes : -p->graph_refused;
 }
+
+int ss_plan_graph_segments(const ss_plan *p) { return p ? (int)p->graph_segments : 0; }
 
 void ss_plan_destroy(ss_plan *p) {
   if (!p) return;

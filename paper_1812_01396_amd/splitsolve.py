@@ -27,7 +27,7 @@ EXPORTS = (
     "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_transmission_noalloc",
     "ss_injection_left", "ss_refine_psi",
     "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
-    "ss_plan_graph_nodes", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
+    "ss_plan_graph_nodes", "ss_plan_graph_segments", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
     "ss_lead_selfenergy_warm", "ss_observables", "ss_energy_integral", "ss_precompute_columns_spike",
 )
@@ -62,7 +62,7 @@ class _PlanOpts(ctypes.Structure):
         ("eta", ctypes.c_double), ("absorb", ctypes.c_double), ("sigma_tol", ctypes.c_double),
         ("sigma_passes", ctypes.c_int),
         ("m", ctypes.c_int), ("use_graph", ctypes.c_int), ("autotune", ctypes.c_int),
-        ("mem_bytes", ctypes.c_size_t),
+        ("mem_bytes", ctypes.c_size_t), ("graph_segment_nodes", ctypes.c_int),
     ]
 
 
@@ -136,6 +136,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_plan_describe.restype = I
     lib.ss_plan_graph_nodes.argtypes = [P]
     lib.ss_plan_graph_nodes.restype = ctypes.c_longlong
+    lib.ss_plan_graph_segments.argtypes = [P]
+    lib.ss_plan_graph_segments.restype = I
     lib.ss_plan_destroy.argtypes = [P]
     lib.ss_plan_destroy.restype = None
     IP = ctypes.POINTER(ctypes.c_int)
@@ -476,7 +478,7 @@ class Plan:
 
     def __init__(self, ctx: Context, instances, eta: float, m: int = 0, use_graph: bool = True,
                  autotune: bool = True, sigma_tol: float = 0.0, sigma_passes: int = 0, mem_bytes: int = 0,
-                 absorb: float = 0.0):
+                 absorb: float = 0.0, graph_segment_nodes: int = 0):
         dev = ctx.device
         n = len(instances)
         if n < 1:
@@ -500,7 +502,7 @@ class Plan:
                                x.Su.data_ptr() if nb > 1 else None, x.H00.data_ptr(), x.H01.data_ptr(),
                                x.S00.data_ptr(), x.S01.data_ptr(), None if x.psi is None else x.psi.data_ptr())
         opts = _PlanOpts(float(eta), float(absorb), float(sigma_tol), int(sigma_passes), int(m), int(bool(use_graph)),
-                         int(bool(autotune)), int(mem_bytes))
+                         int(bool(autotune)), int(mem_bytes), int(graph_segment_nodes))
         self.ctx = ctx
         self.instances = list(instances)
         self.T = torch.zeros(n, 2, dtype=torch.float64, device=dev)
@@ -517,6 +519,10 @@ class Plan:
     @property
     def graph_nodes(self) -> int:
         return int(self.ctx.lib.ss_plan_graph_nodes(self.handle))
+
+    @property
+    def graph_segments(self) -> int:
+        return int(self.ctx.lib.ss_plan_graph_segments(self.handle))
 
     def groups(self):
         """Per group: dict(s, count, chunk, lu_width, tune_ms)."""

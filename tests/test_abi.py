@@ -60,6 +60,7 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.ss_plan_execute(None) == 1
     assert lib.ss_plan_groups(None) == 0
     assert lib.ss_plan_graph_nodes(None) == 0
+    assert lib.ss_plan_graph_segments(None) == 0
     assert lib.ss_plan_describe(None, 0, None, None, None, None, None) == 1
     lib.ss_plan_destroy(None)
 

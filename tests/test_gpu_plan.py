@@ -113,8 +113,10 @@ def test_plan_matches_oracle(ctx, batch, use_graph, autotune):
     plan.close()
 
 
-def test_plan_graph_replays_match_eager(ctx, batch):
-    """Several replays of the captured graph, with other GPU work in between, against an eager plan."""
+@pytest.mark.parametrize("segment_nodes", [0, 96])
+def test_plan_graph_replays_match_eager(ctx, batch, segment_nodes):
+    """Several replays of the captured graph segments (the default segment size, and segments of about 96
+    nodes: dozens of them per group), with other GPU work in between, against an eager plan."""
     import paper_1812_01396_amd as ss
     insts, Es = batch
     m = 8
@@ -125,9 +127,10 @@ def test_plan_graph_replays_match_eager(ctx, batch):
     T0 = eager.T.cpu().numpy()
     psi0 = [x.psi.cpu().numpy() for x in xe]
     xg = _make(ss, insts, Es, m)
-    graph = ss.Plan(ctx, xg, ETA, m=m, use_graph=True, autotune=False)
-    print("graph nodes", graph.graph_nodes, flush=True)
+    graph = ss.Plan(ctx, xg, ETA, m=m, use_graph=True, autotune=False, graph_segment_nodes=segment_nodes)
+    print("graph nodes", graph.graph_nodes, "segments", graph.graph_segments, flush=True)
     assert graph.graph_nodes > 0
+    assert graph.graph_segments >= (graph.graph_nodes // 200 if segment_nodes else len(graph.groups()))
     for rep in range(3):
         graph.T.zero_()
         for x in xg:
@@ -161,8 +164,9 @@ def test_plan_small_memory_runs_one_instance_per_chunk(ctx, batch):
 def test_plan_uneven_workload_sizes_vs_oracle(ctx):
     """One instance of each block size of the uneven 256-instance workload (s = 128, 256, 384, 512, 768, its
     own cell, nb, E and k from that workload's generator, absorbing boundary 1) in one autotuned plan run as
-    the workload runs (its groups' graphs would exceed the node bound, so the groups enqueue from threads of
-    their own): T against the oracle's Caroli pair at 1e-8 (the workload's own bar), every code zero."""
+    the workload runs (each group's work replayed as captured graph segments of at most about 2048 nodes,
+    from threads of their own): T against the oracle's Caroli pair at 1e-8 (the workload's own bar), every
+    code zero."""
     import bench
     import paper_1812_01396_amd as ss
     specs, seen = [], set()
@@ -180,7 +184,10 @@ def test_plan_uneven_workload_sizes_vs_oracle(ctx):
         items.append(ss.Instance(_dev(inst.Hd), _dev(inst.Hu), _dev(inst.Sd), _dev(inst.Su), *[_dev(x) for x in cell],
                                  E))
     print("uneven sizes:", [(s, nb) for s, nb, _, _, _ in specs], flush=True)
-    plan = ss.Plan(ctx, items, bench.UNEVEN["eta"], use_graph=False, autotune=True, absorb=bench.UNEVEN["absorb"])
+    plan = ss.Plan(ctx, items, bench.UNEVEN["eta"], use_graph=True, autotune=True, absorb=bench.UNEVEN["absorb"])
+    print("graph nodes", plan.graph_nodes, "segments", plan.graph_segments, flush=True)
+    assert plan.graph_nodes > 0 and plan.graph_segments >= plan.graph_nodes // 2200
+    plan.T.zero_()
     plan.execute()
     torch.cuda.synchronize()
     T, info = plan.T.cpu().numpy(), plan.info.cpu().numpy()
