@@ -6,8 +6,9 @@
 // fit the plan's memory.  A chunk runs the whole hot path in lockstep: at recursion step t only the
 // instances with more than t blocks are launched, so an uneven chunk does exactly its own work.
 // Groups run on their own streams and overlap.  The enqueued work of each group can be captured once
-// into a graph of its own, so an execution is one graph launch per group.  An autotuner times candidate LU panel widths and
-// chunk sizes per group on the group's own smallest instances before capture.
+// as a short sequence of bounded graph segments, so an execution is a few graph launches per group.  An
+// autotuner times candidate LU panel widths and chunk sizes per group on the group's own smallest
+// instances before capture.
 #include <algorithm>
 #include <cmath>
 #include <map>
