@@ -605,7 +605,7 @@ class Pipeline:
     of G^R, and T.  Outputs stay on the device (sigma, iters, resid, psi, gc, T, info_*).
     """
 
-    def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-12,
+    def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-10,
                  accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0):
         import torch
 
@@ -912,7 +912,7 @@ def main():
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
-    ap.add_argument("--refine-tol", type=float, default=1e-12, help="mixed: relative residual the refinement stops at")
+    ap.add_argument("--refine-tol", type=float, default=1e-10, help="mixed: relative residual the refinement stops at")
     ap.add_argument("--m-inj", type=int, default=0, help="mixed: columns of the injection factor (0: workload's m)")
     ap.add_argument("--roofline-kernel", default="lu_gemm",
                     help="kernel family timed with HIP events for the roofline entry")
