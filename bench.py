@@ -269,6 +269,50 @@ def counter_means(path: str, pattern: str):
     return {q: (len(v), float(np.mean(v)), float(np.max(v))) for q, v in sorted(per.items())}
 
 
+# kernel families of the SQ counter report: (label, name pattern)
+SQ_FAMILIES = [("k_lu_gemm 64x64", r"k_lu_gemm<ss::TileCfg<64, 64"), ("k_lu_gemm 64x32", r"k_lu_gemm<ss::TileCfg<64, 32"),
+               ("k_lu_gemm 32x128", r"k_lu_gemm<ss::TileCfg<32, 128"), ("k_panel32", r"k_panel32<"),
+               ("k_lu_leaf2x", r"k_lu_leaf2x<"), ("k_form", r"k_form<"), ("k_chain", r"k_chain<"),
+               ("k_dec_update", r"k_dec_update")]
+MI355X_SIMDS = 256 * 4
+MI355X_XCDS = 8
+
+
+def sq_report(paths) -> str:
+    """Per-dispatch means of the SQ/GRBM counters that rocprofv3 --pmc wrote (one or more
+    *_counter_collection.csv files, one row per dispatch and counter), per kernel family, with derived
+    ratios: the share of wave time spent waiting to issue (SQ_WAIT_INST_ANY / SQ_WAVE_CYCLES, both in
+    quad-cycles), instructions per wave, the matrix-core busy share (SQ_VALU_MFMA_BUSY_CYCLES summed over
+    the 1024 SIMDs / (1024 x the per-XCD clock cycles, GRBM_GUI_ACTIVE being summed over the 8 XCDs: it
+    reads 8 x 2.38 cycles per ns of dispatch)) and the FP64 matrix flops the hardware counted
+    (MOPS_F64 x 512) per second of the dispatch's duration."""
+    import csv
+    import re
+
+    disp = {}
+    for path in paths:
+        with open(path, newline="") as f:
+            for r in csv.DictReader(f):
+                key = (path, r["Dispatch_Id"])
+                d = disp.setdefault(key, {"name": r["Kernel_Name"], "ns": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+                d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    lines = ["family | dispatches | mean us | waves | wait/wave-cycles | VALU/wave | MFMA/wave | LDS/wave | "
+             "MFMA busy | FP64 MFMA TF/s (counted)"]
+    for label, pat in SQ_FAMILIES:
+        rows = [d for d in disp.values() if re.search(pat, d["name"])]
+        if not rows:
+            continue
+        m = lambda c: float(np.mean([d.get(c, np.nan) for d in rows]))  # noqa: E731
+        us = m("ns") / 1e3
+        waves = m("SQ_WAVES")
+        wait = m("SQ_WAIT_INST_ANY") / max(m("SQ_WAVE_CYCLES"), 1.0)
+        busy = m("SQ_VALU_MFMA_BUSY_CYCLES") / max(m("GRBM_GUI_ACTIVE") / MI355X_XCDS * MI355X_SIMDS, 1.0)
+        tfs = m("SQ_INSTS_VALU_MFMA_MOPS_F64") * 512.0 / max(m("ns"), 1.0) / 1e3
+        lines.append(f"{label} | {len(rows)} | {us:.1f} | {waves:.0f} | {wait:.3f} | {m('SQ_INSTS_VALU') / waves:.0f} | "
+                     f"{m('SQ_INSTS_MFMA') / waves:.0f} | {m('SQ_INSTS_LDS') / waves:.0f} | {busy:.3f} | {tfs:.1f}")
+    return "\n".join(lines)
+
+
 def traffic_report(family: str, workload: str, fetch_csv: str, write_csv: str, copy_fetch_csv: str,
                    copy_write_csv: str, queue: int, algorithmic_bytes: float, commands: str) -> str:
     """The text of profiles/<family>_traffic_<workload>.txt: FETCH_SIZE and WRITE_SIZE per dispatch of the
@@ -927,6 +971,8 @@ def main():
                     help="only print a per-kernel summary of a rocprofv3 kernel trace (*_results.db or "
                          "*kernel_trace.csv) and exit (no GPU needed)")
     ap.add_argument("--trace-steps", type=int, default=1, help="--summarize-trace: steps the trace covers")
+    ap.add_argument("--sq-report", nargs="+", default=None, metavar="CSV",
+                    help="summarise rocprofv3 --pmc counter CSVs (SQ and GRBM counters) per kernel family and exit")
     ap.add_argument("--traffic-report", nargs=8, default=None,
                     metavar=("FAMILY", "FETCH_CSV", "WRITE_CSV", "COPY_FETCH_CSV", "COPY_WRITE_CSV", "QUEUE",
                              "ALG_BYTES", "COMMANDS"),
@@ -947,6 +993,9 @@ def main():
             for name, pat in (("k_lu_gemm", r"k_lu_gemm<"), ("k_dec_update", r"k_dec_update")):
                 for q, (n, avg) in trace_queue_stats(args.summarize_trace, pat).items():
                     print(f"# {name} on queue {q}: {n} launches, average {avg:.1f} us")
+        return
+    if args.sq_report:
+        print(sq_report(args.sq_report))
         return
     if args.traffic_report:
         fam, fcsv, wcsv, cfcsv, cwcsv, q, alg, cmds = args.traffic_report
