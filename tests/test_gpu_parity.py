@@ -201,11 +201,13 @@ def test_chain_crystal_all_energies(ctx, absorb):
         assert abs(out["T"][b, 0] - ref["t_lr"]) <= TOL * max(1.0, ref["t_lr"])
 
 
-@pytest.mark.parametrize("n,nmat", [(1, 2), (33, 3), (84, 2), (100, 2), (250, 2), (512, 3), (700, 2), (1100, 1)])
+@pytest.mark.parametrize("n,nmat", [(1, 2), (33, 3), (84, 2), (100, 2), (250, 2), (512, 3), (700, 2), (1100, 1),
+                                    (1536, 1), (2048, 1)])
 def test_lu_factor_vs_oracle(ctx, n, nmat):
     """The batched LU (panel widths 32, 16 and 8 by order) takes the oracle's pivots exactly and its
     factors agree element by element (rounding-order differences only).  Orders 84 and 250 end in
-    panels of 20 and 26 columns: full and partial 8-column quarters."""
+    panels of 20 and 26 columns: full and partial 8-column quarters.  Orders 1536 and 2048 (the corner
+    systems of s = 768 and s = 1024) run the 8-column panel with two rows per thread."""
     import paper_1812_01396_amd as ss
     print(f"lu_factor n={n} nmat={nmat}", flush=True)
     rng = np.random.default_rng(n + nmat)
