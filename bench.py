@@ -657,7 +657,8 @@ class Pipeline:
 
         self.ss, self.torch = ss, torch
         self.mode = mode
-        self.prec = {"fp64": ss.SS_PREC_FP64, "mixed": ss.SS_PREC_FP32, "mixed-lu": ss.SS_PREC_FP32_LU}[mode]
+        self.prec = {"fp64": ss.SS_PREC_FP64, "mixed": ss.SS_PREC_FP32, "mixed-lu": ss.SS_PREC_FP32_LU,
+                     "mixed-bf16": ss.SS_PREC_BF16}[mode]
         self.refine_tol = refine_tol
         self.accept_tol = accept_tol  # refined residual above this: the instance is redone in FP64
         self.fallback = 0
@@ -901,16 +902,17 @@ def run_spike(args):
 
 
 def compare_precisions(workload: str, steps: int = 1, warmup: int = 1):
-    """One timed step of `workload` in plain FP64 and in mixed precision (FP32 products in the block
-    formations and the chain, FP64 refinement of psi, T from the refined psi with the broadening tail),
-    each after `warmup` untimed steps: solves/s and T against the stored oracle values, so that every
-    default benchmark line carries the plain-FP64-versus-mixed comparison of the same configuration."""
+    """One timed step of `workload` in plain FP64 and in the two mixed forms (the block formations and the
+    chain with FP32 products, or with BF16-term products on the BF16 matrix cores; FP64 refinement of
+    psi, T from the refined psi with the broadening tail), each after `warmup` untimed steps: solves/s and
+    T against the stored oracle values, so that every default benchmark line carries the
+    plain-FP64-versus-mixed comparison of the same configuration."""
     import gc
 
     import torch
 
     res = {}
-    for mode in ("fp64", "mixed"):
+    for mode in ("fp64", "mixed", "mixed-bf16"):
         print(f"{workload} {mode}: building the pipeline", file=sys.stderr, flush=True)
         pipe = Pipeline(workload, mode=mode)
         for _ in range(warmup):
@@ -950,8 +952,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="uneven256: default panel widths and chunks")
     ap.add_argument("--plan-mem-gib", type=float, default=0.0,
                     help="uneven256: chunk work memory (0: the device memory left after the inputs, less 4 GiB)")
-    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "mixed-lu"],
-                    help="mixed: FP32 products in the block formations and the chain; mixed-lu: also in the LU")
+    ap.add_argument("--mode", default="fp64", choices=["fp64", "mixed", "mixed-lu", "mixed-bf16"],
+                    help="mixed: FP32 products in the block formations and the chain; mixed-lu: also in the LU; "
+                         "mixed-bf16: those of mixed from BF16 terms on the BF16 matrix cores")
     ap.add_argument("--absorb", type=float, default=-1.0,
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")

@@ -157,6 +157,9 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
                           /* formations and the chain; the LU stays FP64                        */
 #define SS_PREC_FP32_LU 2 /* as SS_PREC_FP32, and the LU's trailing and triangular-solve        */
                           /* updates in FP32 too (less accurate factors: more refinement passes) */
+#define SS_PREC_BF16 3    /* the products of SS_PREC_FP32 on the BF16 matrix cores: every operand  */
+                          /* split into three BF16 terms, the six term products of FP32 order,  */
+                          /* FP32 accumulation; the LU stays FP64                               */
 
 /* flags of ss_precompute_columns */
 #define SS_KEEP_FACTORS 1 /* keep the first-column recursion's factors in the context for     */

@@ -14,6 +14,7 @@ from .splitsolve import (  # noqa: F401
     load_library,
     SS_PREC_FP32,
     SS_PREC_FP32_LU,
+    SS_PREC_BF16,
     SS_PREC_FP64,
     ss_apply_obc,
     ss_energy_integral,

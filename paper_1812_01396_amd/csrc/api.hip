@@ -214,9 +214,10 @@ size_t lu_inverse_bytes(size_t nmat, int n) {
 ss_status ss_workspace_size(int batch, int nb, int s, int m, int prec, int flags, size_t *bytes) {
   if (!bytes || batch < 0 || nb < 1 || s < 1 || m < 0) return SS_ERR_ARG;
   if (s > SS_MAX_S) return SS_ERR_UNSUPPORTED;
-  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU) return SS_ERR_ARG;
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU && prec != SS_PREC_BF16) return SS_ERR_ARG;
   // the requests of the four steps in their order, mirroring the drivers (the decimation, the
-  // recursion's sweep, the corner system, the transmission); the precision does not change them
+  // recursion's sweep, the corner system, the transmission); the precision adds the FP32 coupling
+  // blocks of the BF16-term products
   size_t h[kNumSlots] = {};
   const size_t c = sizeof(double2), i4 = sizeof(int), b = (size_t)batch, S = (size_t)s, ss2 = S * S;
   // ss_lead_selfenergy: decimation state and systems, then the final solves
@@ -232,6 +233,7 @@ ss_status ss_workspace_size(int batch, int nb, int s, int m, int prec, int flags
   ws_request(h, kSlotPerm, i4 * 2 * b * S);
   ws_request(h, kSlotZp, i4 * 3 * b);
   ws_request(h, kSlotX, c * 2 * b * (size_t)nb * ss2);
+  if (prec == SS_PREC_BF16) ws_request(h, kSlotCpl, sizeof(float2) * 2 * b * ss2);
   if (flags & SS_KEEP_FACTORS) {
     ws_request(h, kSlotFact, c * b * (size_t)nb * ss2);
     ws_request(h, kSlotFactPerm, i4 * b * (size_t)nb * S);
@@ -310,7 +312,7 @@ ss_status ss_precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const 
   if (batch == 0) return SS_OK;
   if (!hs->H_diag || !hs->S_diag || !E || !Q || (hs->nb > 1 && (!hs->H_upper || !hs->S_upper)))
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: null input or output pointer");
-  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU)
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU && prec != SS_PREC_BF16)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown precision");
   if (flags & ~SS_KEEP_FACTORS) return fail(ctx, SS_ERR_ARG, "ss_precompute_columns: unknown flags");
   if (!(absorb >= 0.0) || !std::isfinite(absorb))
@@ -327,7 +329,7 @@ ss_status ss_precompute_columns_spike(ss_ctx *ctx, const ss_btd *hs, int batch, 
   if (hs->s > SS_MAX_S) return fail(ctx, SS_ERR_UNSUPPORTED, "ss_precompute_columns_spike: s > SS_MAX_S");
   if (nparts < 1 || nparts > hs->nb || (nparts & (nparts - 1)) != 0)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: nparts must be a power of two in [1, nb]");
-  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU)
+  if (prec != SS_PREC_FP64 && prec != SS_PREC_FP32 && prec != SS_PREC_FP32_LU && prec != SS_PREC_BF16)
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: unknown precision");
   if (!(absorb >= 0.0) || !std::isfinite(absorb))
     return fail(ctx, SS_ERR_ARG, "ss_precompute_columns_spike: absorb must be finite and >= 0");

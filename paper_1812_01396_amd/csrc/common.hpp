@@ -88,6 +88,7 @@ enum Slot {
   kSlotMlpDz,      // back-propagated gradients
   kSlotLuInv,      // inverses of the LU's diagonal blocks (triangular-solve leaves)
   kSlotSpike,      // partition tables, the second column buffer and the interface systems of the merges
+  kSlotCpl,        // FP32 coupling blocks of the next recursion step (BF16-term products)
   kNumSlots
 };
 

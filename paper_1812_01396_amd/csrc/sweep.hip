@@ -23,6 +23,7 @@
 #include "drivers.hpp"
 #include "tile.hpp"
 #include "tile32.hpp"
+#include "tilebf.hpp"
 
 namespace ss {
 
@@ -42,6 +43,7 @@ struct SweepArgs {
   int *code;   // [batch] smallest zero-pivot code, INT_MAX if none
   double2 *X;  // per system: one s x s slot per block, packed (system 2i+d at block 2 boff(i) + d nb(i))
   double2 *Q;  // per instance [nb][s][2s], packed at block boff(i)
+  float2 *cpl;  // per system [s][s]: the next step's coupling block in FP32 (BF16-term products only)
   int *info;   // [batch] or null
   int batch;
 };
@@ -69,20 +71,41 @@ __device__ __forceinline__ double2 *xslot(const SweepArgs &a, int mat, int t) {
   return a.X + (2 * boff_of(a, inst) + (long)dir * nb_of(a, inst) + t) * ((long)a.s * a.s);
 }
 
+// element (r, c) of an FP32 complex row-major block
+struct LdRowF32 {
+  const float2 *p;
+  long ld;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int r, int c) const {
+    const float2 v = p[(long)r * ld + c];
+    return make_double2(v.x, v.y);
+  }
+};
+
 using FormTile = TileCfg<64, 64, 16, 2, 2>;
 using FormTile32 = TileCfg32<64, 64, 16, 2, 2>;
+using FormTileB = TileCfgB<64, 64, 32, 2, 2, 3>;
 static_assert(FormTile32::LDS_FLOATS <= 2 * FormTile::LDS_DOUBLES, "shared staging buffer too small");
+static_assert(FormTileB::NT == FormTile::NT, "one workgroup shape for every precision");
 
-// acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in FP64 (kF32 == false) or with FP32 operands
-// and FP32 accumulation (kF32 == true); f(r, c, value) receives every element of the tile.
-template <bool kF32, class LA, class LB, class F>
+// precision of the block products: FP64, FP32, or BF16 terms (three per operand) with FP32 accumulation
+enum { kProdF64 = 0, kProdF32 = 1, kProdBF16 = 2 };
+
+// acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in the precision kP; f(r, c, value) receives
+// every element of the tile.
+template <int kP, class LA, class LB, class F>
 __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0, int M, int n0, int N, int kbeg,
                                              int kend, double *lds, F &&f) {
-  if constexpr (kF32) {
+  if constexpr (kP == kProdF32) {
     Acc32<FormTile32> acc;
     acc.zero();
     mma_loop32<FormTile32>(la, lb, m0, M, n0, N, kbeg, kend, acc, reinterpret_cast<float *>(lds));
     acc_foreach32<FormTile32>(acc, f);
+  } else if constexpr (kP == kProdBF16) {
+    AccB<FormTileB> acc;
+    acc.zero();
+    mma_loop_bf<FormTileB>(la, lb, m0, M, n0, N, kbeg, kend, acc, reinterpret_cast<unsigned short *>(lds));
+    acc_foreach_bf<FormTileB>(acc, f);
   } else {
     Acc<FormTile> acc;
     acc.zero();
@@ -92,11 +115,10 @@ __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0,
 }
 
 // Forms [D | RHS] of step t for every system; fold the previous step's zero pivot into `code`.
-template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES
-k_form(SweepArgs a, int t) {
+// kPart 0: the grid covers the D tiles and then the RHS tiles; 1: the D tiles only; 2: the RHS tiles only.
+template <int kP, int kPart>
+__device__ __forceinline__ void form_body(const SweepArgs &a, int t, double *lds) {
   using T = FormTile;
-  __shared__ double lds[T::LDS_DOUBLES];
   int tile, mat;
   xcd_tile_order(tile, mat);
   const int inst = mat >> 1, dir = mat & 1;
@@ -111,6 +133,7 @@ k_form(SweepArgs a, int t) {
   double2 *M = a.M + (long)mat * 2 * ss2;
   const int tiles = cdiv(s, T::BM);
   const int ntile = tiles * tiles;
+  if (kPart == 2) tile += ntile;
 
   if (tile == 0 && threadIdx.x == 0 && t > 0) {
     const int z = a.zp[mat];
@@ -121,6 +144,7 @@ k_form(SweepArgs a, int t) {
   }
 
   if (tile < ntile) {
+    if constexpr (kPart != 2) {
     // D tile: D = A_ib,ib - coupling * previous solution
     const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
     // absorbing shift of the boundary blocks (both of them when nb == 1)
@@ -136,12 +160,34 @@ k_form(SweepArgs a, int t) {
     if (t > 0) {
       const double2 *xp = xslot(a, mat, t - 1);
       LdRow lb{xp, s};
-      if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
+      if constexpr (kP == kProdBF16) {  // the coupling block, formed in FP32 by the previous step
+        using TB = FormTileB;
+        LdRowF32 la{a.cpl + (long)mat * ss2, s};
+        AccB<TB> acc;
+        acc.zero();
+        mma_loop_bf<TB>(la, lb, m0, s, n0, s, 0, s, acc, reinterpret_cast<unsigned short *>(lds));
+        // the epilogue reads every A_ii element of this thread before it writes any of D, so the
+        // loads are in flight together (two waves per SIMD hide little latency)
+        double2 av[TB::FM * TB::FN * 4];
+        int i = 0;
+        acc_foreach_bf<TB>(acc, [&](int r, int c, double2) {
+          const int gr = m0 + r, gc = n0 + c;
+          const long o = (long)min(gr, s - 1) * s + min(gc, s - 1);
+          const double2 hv = hd[o], sv = sd[o];
+          av[i++] = make_double2(e * sv.x - hv.x, e * sv.y - hv.y + (gr == gc ? shift : 0.0));
+        });
+        i = 0;
+        acc_foreach_bf<TB>(acc, [&](int r, int c, double2 v) {
+          const int gr = m0 + r, gc = n0 + c;
+          const double2 w = av[i++];
+          if (gr < s && gc < s) M[(long)gr * 2 * s + gc] = csub(w, v);
+        });
+      } else if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
         LdForm<false> la{blk(a, ks, 1, ib), blk(a, ks, 3, ib), s, e};
-        tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
+        tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, store);
       } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
         LdForm<true> la{blk(a, ks, 1, ib - 1), blk(a, ks, 3, ib - 1), s, e};
-        tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, store);
+        tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, store);
       }
     } else {
       for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT)
@@ -151,7 +197,8 @@ k_form(SweepArgs a, int t) {
       for (int r = threadIdx.x; r < T::BM; r += T::NT)
         if (m0 + r < s) a.perm[(long)mat * s + m0 + r] = m0 + r;
     }
-  } else {
+    }
+  } else if constexpr (kPart != 1) {
     // RHS tile: the coupling to the already-eliminated side, or the identity at the boundary
     tile -= ntile;
     const int m0 = (tile / tiles) * T::BM, n0 = (tile % tiles) * T::BN;
@@ -159,6 +206,10 @@ k_form(SweepArgs a, int t) {
     const int ub = dir == 0 ? ib - 1 : ib;
     const double2 *hu = blk(a, ks, 1, std::max(ub, 0));
     const double2 *su = blk(a, ks, 3, std::max(ub, 0));
+    // with BF16-term products, the next step's coupling block (the conjugate transpose of this RHS)
+    // is also written, in FP32: A_{ib-1,ib} = E S_u - H_u (direction 0), A_{ib+1,ib} = its transpose
+    // conjugate (direction 1)
+    float2 *cp = (kPart == 2 && !ident) ? a.cpl + (long)mat * ss2 : nullptr;
     for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
       const int r = idx / T::BN, c = idx % T::BN;
       const int gr = m0 + r, gc = n0 + c;
@@ -173,6 +224,17 @@ k_form(SweepArgs a, int t) {
         v = make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
       }
       M[(long)gr * 2 * s + s + gc] = v;
+      if (cp) {
+        double2 w;
+        if (dir == 0) {
+          const long o = (long)gr * s + gc;
+          w = make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
+        } else {
+          const long o = (long)gc * s + gr;
+          w = make_double2(e * su[o].x - hu[o].x, -(e * su[o].y - hu[o].y));
+        }
+        cp[(long)gr * s + gc] = make_float2((float)w.x, (float)w.y);
+      }
     }
   }
 }
@@ -197,12 +259,27 @@ __global__ void k_code_init(int *code, int n) {
   if (i < n) code[i] = INT_MAX;
 }
 
-// Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES
-k_chain(SweepArgs a, int u) {
+__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES k_form(SweepArgs a, int t) {
+  __shared__ double lds[FormTile::LDS_DOUBLES];
+  form_body<kF32 ? kProdF32 : kProdF64, 0>(a, t, lds);
+}
+
+// The BF16-term products need 60 KB of staging: two workgroups per CU, so two waves' registers per SIMD.
+// The RHS tiles, plain element-wise formation, go to k_form_rhs, which runs at full occupancy.
+__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(2))) k_form_bf(SweepArgs a, int t) {
+  __shared__ double lds[FormTileB::LDS_BYTES / 8];
+  form_body<kProdBF16, 1>(a, t, lds);
+}
+
+__global__ void __launch_bounds__(FormTile::NT) k_form_rhs(SweepArgs a, int t) {
+  form_body<kProdF64, 2>(a, t, nullptr);
+}
+
+// Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
+template <int kP>
+__device__ __forceinline__ void chain_body(const SweepArgs &a, int u, double *lds) {
   using T = FormTile;
-  __shared__ double lds[T::LDS_DOUBLES];
   int tile, mat;
   xcd_tile_order(tile, mat);
   const int inst = mat >> 1, dir = mat & 1;
@@ -226,10 +303,21 @@ k_chain(SweepArgs a, int u) {
   const double2 *qp = q0 + (long)pb * 2 * ss2;
   LdRow la{x, s};
   LdRow lb{qp, 2 * s};
-  tile_product<kF32>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
+  tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < s && gc < s) qi[(long)gr * 2 * s + gc] = cneg(v);
   });
+}
+
+template <bool kF32>
+__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES k_chain(SweepArgs a, int u) {
+  __shared__ double lds[FormTile::LDS_DOUBLES];
+  chain_body<kF32 ? kProdF32 : kProdF64>(a, u, lds);
+}
+
+__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(2))) k_chain_bf(SweepArgs a, int u) {
+  __shared__ double lds[FormTileB::LDS_BYTES / 8];
+  chain_body<kProdBF16>(a, u, lds);
 }
 
 // Keep the factorization of the first-column recursion's step t (L\U in physical rows and the row
@@ -267,6 +355,12 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
   a.zp = (int *)wZ;
   a.code = (int *)wZ + nmat;
   a.X = (double2 *)wX;
+  a.cpl = nullptr;
+  if (prec == SS_PREC_BF16) {
+    void *wC;
+    SS_TRY(workspace(ctx, kSlotCpl, sizeof(float2) * nmat * (size_t)ss2, &wC));
+    a.cpl = (float2 *)wC;
+  }
 
   LuDesc d;
   d.n = n;
@@ -297,7 +391,10 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
     if (na <= 0) break;
     {
       KernelScope ks_(ctx, "form");
-      if (f32)
+      if (prec == SS_PREC_BF16) {  // the product reads the coupling block before the RHS kernel replaces it
+        hipLaunchKernelGGL(k_form_bf, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, t);
+        hipLaunchKernelGGL(k_form_rhs, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, t);
+      } else if (f32)
         hipLaunchKernelGGL(k_form<true>, dim3(2 * tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, t);
       else
         hipLaunchKernelGGL(k_form<false>, dim3(2 * tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a,
@@ -315,7 +412,9 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
     const int na = act[u];
     if (na <= 0) break;
     KernelScope ks_(ctx, "chain");
-    if (f32)
+    if (prec == SS_PREC_BF16)
+      hipLaunchKernelGGL(k_chain_bf, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, u);
+    else if (f32)
       hipLaunchKernelGGL(k_chain<true>, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, u);
     else
       hipLaunchKernelGGL(k_chain<false>, dim3(tiles * tiles, 2 * na), dim3(FormTile::NT), 0, ctx->stream, a, u);

@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsplitsolve.so")
 
 SS_OK, SS_ERR_ARG, SS_ERR_NOMEM, SS_ERR_DEVICE, SS_ERR_UNSUPPORTED = range(5)
 SS_MAX_S = 1024
-SS_PREC_FP64, SS_PREC_FP32, SS_PREC_FP32_LU = 0, 1, 2
+SS_PREC_FP64, SS_PREC_FP32, SS_PREC_FP32_LU, SS_PREC_BF16 = 0, 1, 2, 3
 SS_KEEP_FACTORS = 1
 
 EXPORTS = (
@@ -308,7 +308,7 @@ def ss_precompute_columns(ctx: Context, Hd, Hu, Sd, Su, E, kidx=None, Q=None, in
     """Q = first and last block columns of (E S - H)^{-1} for every instance (Sec. 3B, Step 1).
 
     Hd, Sd: [nk, nb, s, s]; Hu, Su: [nk, nb-1, s, s] (or without the leading nk).  E: [batch] float64.
-    prec: SS_PREC_FP64, SS_PREC_FP32 or SS_PREC_FP32_LU (products of the recursion); keep_factors keeps the first-column
+    prec: SS_PREC_FP64, SS_PREC_FP32, SS_PREC_FP32_LU or SS_PREC_BF16 (products of the recursion); keep_factors keeps the first-column
     recursion's factors in the context for ss_refine_psi; absorb: absorbing boundary (i*absorb*I on the
     first and last diagonal blocks; pass the same value to ss_apply_obc).  Returns (Q [batch, nb, s, 2s],
     info [batch]).

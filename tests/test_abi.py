@@ -93,6 +93,10 @@ def test_workspace_size_query_host_side(lib):
     assert q(0, 4, 16) == 0
     assert 0 < q(2, 4, 16, 3) < q(4, 4, 16, 3) < q(4, 9, 16, 3)
     assert q(4, 9, 16, 3, flags=splitsolve.SS_KEEP_FACTORS) > q(4, 9, 16, 3)
+    # the BF16-term products add the FP32 coupling blocks of both recursions: 2 * batch * s^2 * 8 bytes,
+    # as a grow-only workspace grants it (9/8 of the request)
+    bf = q(4, 9, 16, 3, prec=splitsolve.SS_PREC_BF16) - q(4, 9, 16, 3)
+    assert bf == 2 * 4 * 16 * 16 * 8 * 9 // 8
     for bad in [(-1, 4, 16), (2, 0, 16), (2, 4, 0)]:
         with pytest.raises(splitsolve.SplitSolveError):
             q(*bad)

@@ -267,9 +267,11 @@ def test_lu_factor_zero_pivots(ctx):
     assert list(info.cpu().numpy()) == [18, 40]
 
 
-@pytest.mark.parametrize("batch,nb,s,m,keep", [(3, 4, 40, 3, False), (2, 3, 130, 5, True), (1, 1, 16, 0, False)])
-def test_workspace_size_matches_a_fresh_context(batch, nb, s, m, keep):
-    """ss_workspace_size equals what a fresh context holds after one pass of the four steps."""
+@pytest.mark.parametrize("batch,nb,s,m,keep,prec", [(3, 4, 40, 3, False, 0), (2, 3, 130, 5, True, 0),
+                                                    (1, 1, 16, 0, False, 0), (2, 3, 130, 5, True, 3)])
+def test_workspace_size_matches_a_fresh_context(batch, nb, s, m, keep, prec):
+    """ss_workspace_size equals what a fresh context holds after one pass of the four steps (with the
+    BF16-term products: also their FP32 coupling blocks)."""
     import paper_1812_01396_amd as ss
     c = ss.Context(0)
     try:
@@ -279,12 +281,12 @@ def test_workspace_size_matches_a_fresh_context(batch, nb, s, m, keep):
         E = _dev(np.linspace(-0.4, 0.4, batch), torch.float64)
         kidx = torch.arange(batch, dtype=torch.int32, device="cuda")
         sig, _, _, _ = ss.ss_lead_selfenergy(c, *leads, E, 1e-8, kidx=kidx)
-        q, _ = ss.ss_precompute_columns(c, hd, hu, sd, su, E, kidx=kidx, keep_factors=keep, absorb=1.0)
+        q, _ = ss.ss_precompute_columns(c, hd, hu, sd, su, E, kidx=kidx, keep_factors=keep, absorb=1.0, prec=prec)
         inj = _dev(np.stack([synth.injection_block(s, m, 5 + b) for b in range(batch)])) if m else None
         _, gc, _ = ss.ss_apply_obc(c, q, sig, inj=inj, absorb=1.0)
         ss.ss_transmission(c, gc, sig)
         torch.cuda.synchronize()
         flags = ss.splitsolve.SS_KEEP_FACTORS if keep else 0
-        assert c.workspace_bytes() == ss.ss_workspace_size(batch, nb, s, m, flags=flags)
+        assert c.workspace_bytes() == ss.ss_workspace_size(batch, nb, s, m, prec=prec, flags=flags)
     finally:
         c.close()

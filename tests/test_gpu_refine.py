@@ -76,7 +76,7 @@ def test_injection_factor_reproduces_gamma(ctx):
         assert 1 <= out["rank"][b] <= 24
 
 
-@pytest.mark.parametrize("prec,absorb", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0), (2, 1.0)])
+@pytest.mark.parametrize("prec,absorb", [(0, 0.0), (1, 0.0), (0, 1.0), (1, 1.0), (2, 1.0), (3, 0.0), (3, 1.0)])
 def test_refined_psi_matches_oracle(ctx, prec, absorb):
     """Refinement of psi on the open system from the kept factors, for the paper's split and for the
     absorbing one (the factors of A' and C' = Sigma + i*absorb*I)."""
@@ -101,7 +101,7 @@ def test_refined_psi_matches_oracle(ctx, prec, absorb):
         assert out["resid"][b] <= 1e-12
 
 
-@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("prec", [0, 1, 3])
 def test_transmission_from_refined_psi(ctx, prec):
     inst = synth.random_btd(5, 32, seed=808)
     Es = np.array([-0.5, 0.1, 0.6])
@@ -113,7 +113,7 @@ def test_transmission_from_refined_psi(ctx, prec):
         assert abs(out["T_psi"][b] - ref["t_rl"]) <= 1e-8 * max(1.0, ref["t_rl"]), (E, out["T_psi"][b], ref)
 
 
-@pytest.mark.parametrize("prec,absorb", [(0, 1.0), (1, 1.0), (1, 0.0), (2, 1.0)])
+@pytest.mark.parametrize("prec,absorb", [(0, 1.0), (1, 1.0), (1, 0.0), (2, 1.0), (3, 1.0)])
 def test_transmission_tail_of_truncated_injection(ctx, prec, absorb):
     """Injection truncated to the open channels (pivoted Cholesky stopped at 1e-5 of the largest pivot):
     T from psi alone misses the broadening tail of Gamma_L (~1e-6 here), and with the tail added back
@@ -130,6 +130,32 @@ def test_transmission_tail_of_truncated_injection(ctx, prec, absorb):
         assert abs(out["T_psi"][b] - ref["t_rl"]) > 1e-7        # the tail is visible without the correction
         tol = 1e-10 if prec == 0 else 1e-8
         assert abs(out["T_tail"][b] - ref["t_rl"]) <= tol * max(1.0, ref["t_rl"]), (E, out["T_tail"][b], ref["t_rl"])
+
+
+@pytest.mark.parametrize("s", [40, 96])
+def test_bf16_term_products_reach_fp32_accuracy(ctx, s):
+    """Q from the BF16-term products (three BF16 terms per operand, six term products, FP32 accumulation)
+    is as accurate as Q from FP32 products, against the FP64 Q of the same inputs: a dropped term or a
+    wrong sign of the imaginary parts would leave errors of order 2^-8 or worse; one BF16 term alone
+    would leave about 1e-3.  s = 40 and 96 exercise partial 64-wide tiles and partial 32-deep stages."""
+    import paper_1812_01396_amd as ss
+    nb = 4
+    insts = [synth.random_btd(nb, s, seed=1200 + s + k) for k in range(2)]
+    Es = np.array([0.17, -0.41])
+    kidx = np.array([0, 1], np.int32)
+    hd, hu, sd, su = (_dev(np.stack([getattr(i, f) for i in insts])) for f in ("Hd", "Hu", "Sd", "Su"))
+    E_d, k_d = _dev(Es, torch.float64), _dev(kidx, torch.int32)
+    qs = {}
+    for prec in (0, 1, 3):
+        q, info = ss.ss_precompute_columns(ctx, hd, hu, sd, su, E_d, kidx=k_d, prec=prec, absorb=1.0)
+        torch.cuda.synchronize()
+        assert int((info != 0).sum()) == 0
+        qs[prec] = q.cpu().numpy()
+    for b in range(2):
+        e32, ebf = _rel(qs[1][b], qs[0][b]), _rel(qs[3][b], qs[0][b])
+        print(f"s={s} b={b}: FP32 products {e32:.2e}, BF16 terms {ebf:.2e}", flush=True)
+        assert 0 < ebf <= 4 * e32 + 1e-7, (b, e32, ebf)
+        assert ebf <= 1e-5
 
 
 def test_crystal_near_closed_device_eigenvalue(ctx):
