@@ -170,8 +170,9 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
  * Backward recursion X_{n_B+1} = 0, (A_{i,i} - A_{i,i+1} X_{i+1}) X_i = A_{i,i-1} with A_{1,0} := I,
  * then Q_i = -X_i Q_{i-1} from Q_0 = -I, gives the first block column; the mirrored recursion (from
  * block 1 upwards with A_{n_B,n_B+1} := I) gives the last one.  Each diagonal system is solved by LU
- * with partial pivoting on the GPU.  prec: SS_PREC_FP64 or SS_PREC_FP32 (see above); flags: 0 or
- * SS_KEEP_FACTORS.
+ * with partial pivoting on the GPU.  prec: SS_PREC_FP64, SS_PREC_FP32, SS_PREC_FP32_LU or SS_PREC_BF16
+ * (see above; SS_PREC_BF16 also holds the next step's coupling blocks in FP32, 8 s^2 bytes per
+ * system); flags: 0 or SS_KEEP_FACTORS.
  *
  * absorb (>= 0, finite): absorbing boundary.  The open system is T = A - B C with B the identity blocks
  * at the top and bottom and C holding the self-energies (Sec. 3B, Eq. (x)); the section leaves the
