@@ -766,13 +766,14 @@ class Pipeline:
             else:
                 ss.ss_transmission(self.ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
 
-    def recursion_alone(self):
+    def recursion_alone(self, family=RECURSION_FAMILIES, with_flops=False):
         """Step 1 by itself (no self-energies beside it): wall time (ms) of ss_precompute_columns over
-        all instances, and the summed duration of its kernels (HIP events)."""
+        all instances, and the summed duration of the launches of `family` (HIP events; all of the
+        recursion's kernels by default); with_flops: also their launch count and algorithmic flops."""
         ss, torch = self.ss, self.torch
         mixed = self.mode != "fp64"
         torch.cuda.synchronize()
-        self.ctx.kernel_timer(RECURSION_FAMILIES)
+        self.ctx.kernel_timer(family)
         t0 = time.perf_counter()
         for c0 in range(0, self.n, self.chunk):
             c1 = min(c0 + self.chunk, self.n)
@@ -782,9 +783,11 @@ class Pipeline:
                                      keep_factors=mixed, absorb=self.absorb)
         torch.cuda.synchronize()
         wall = (time.perf_counter() - t0) * 1e3
-        kms = self.ctx.kernel_timer_read()[0]
+        rd = self.ctx.kernel_timer_read(with_flops=with_flops)
         self.ctx.kernel_timer(None)
-        return wall, kms
+        if with_flops:
+            return wall, rd[0], rd[1], rd[2]
+        return wall, rd[0]
 
     def observables(self):
         """Orbital density and bond currents of every instance's psi (ss_observables, after a step), timed
@@ -1054,10 +1057,16 @@ def main():
     # one more (untimed) step with the recursion's kernels bracketed by HIP events: recursion TFLOP/s
     rec_ms, rec_alone_wall, rec_alone_kms = [], None, None
     obs = None
+    fam_alone = None
     if not args.no_extra:
         pipe.run(recursion_ms=rec_ms)
         torch.cuda.synchronize()
         rec_alone_wall, rec_alone_kms = pipe.recursion_alone()
+        if fam in ("lu_gemm", "form", "chain", "panel", "trsm"):
+            # the roofline kernel's launches in Step 1 run by itself: the same family, nothing beside it
+            _, a_ms, a_n, a_flops = pipe.recursion_alone(fam, with_flops=True)
+            if a_n > 0 and a_flops > 0:
+                fam_alone = (a_ms, a_n, a_flops)
         obs = pipe.observables()
 
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
@@ -1088,6 +1097,13 @@ def main():
                     launches=int(k_launches), avg_launch_ms=round(k_ms / k_launches, 4))
         if k_bytes > 0:
             roof["algorithmic_bytes"] = k_bytes / k_launches
+        if fam_alone is not None:
+            # the same kernel family in Step 1 run by itself after the timed steps (the frac above is
+            # inside the step, where the self-energy stream shares the matrix cores)
+            a_ms, a_n, a_flops = fam_alone
+            a_ach = a_flops / (a_ms * 1e-3) / 1e12
+            roof["alone"] = dict(achieved=round(a_ach, 3), frac=round(a_ach / peak, 4), launches=int(a_n),
+                                 avg_launch_ms=round(a_ms / a_n, 4), scope="Step 1 by itself")
 
     cpu = None
     t_err = None
