@@ -114,9 +114,9 @@ __global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cq(ObcArgs a)
   });
 }
 
-// C Q b' into the last m columns of the augmented matrix
-__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cqb(ObcArgs a) {
-  using T = ObcTile;
+// C Q b' into the last m columns of the augmented matrix (m columns: 64 x 32 tiles)
+__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES k_obc_cqb(ObcArgs a) {
+  using T = PsiTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;
   const int tc = cdiv(m, T::BN);
@@ -204,7 +204,8 @@ static ss_status obc_run(ss_ctx *ctx, ObcArgs &a, int nb_max, bool want_psi, int
   }
   if (m > 0) {
     KernelScope ks_(ctx, "obc");
-    hipLaunchKernelGGL(k_obc_cqb, dim3(cdiv(2 * s, T::BM) * cdiv(m, T::BN), batch), dim3(T::NT), 0, ctx->stream, a);
+    hipLaunchKernelGGL(k_obc_cqb, dim3(cdiv(2 * s, PsiTile::BM) * cdiv(m, PsiTile::BN), batch), dim3(PsiTile::NT), 0,
+                       ctx->stream, a);
   }
   LuDesc d;
   d.nmat = batch;

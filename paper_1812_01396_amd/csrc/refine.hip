@@ -21,7 +21,9 @@
 
 namespace ss {
 
-using RefTile = TileCfg<64, 64, 16, 2, 2>;
+// the products of the refinement have m (the injected modes, typically 32) columns: 64 x 32 tiles, no
+// padded half tile
+using RefTile = TileCfg<64, 32, 16, 4, 1>;
 
 struct LdRowNeg {  // -p[r * ld + c]
   const double2 *p;
@@ -450,7 +452,7 @@ __global__ void __launch_bounds__(1024) k_inject_left(const double2 *sigma, int 
   if (tid == 0 && rank) rank[inst] = k;
 }
 
-using TpTile = TileCfg<64, 64, 16, 2, 2>;
+using TpTile = TileCfg<64, 32, 16, 4, 1>;
 
 // partial sums of Re sum_{a,c} conj(psi[a][c]) (Gamma_R psi)[a][c] over tiles of the last block row
 __global__ void __launch_bounds__(TpTile::NT) SS_TILE_WAVES k_trans_psi(const double2 *psi, const double2 *sigma, int nb, int s,
