@@ -237,6 +237,7 @@ ss_status ss_workspace_size(int batch, int nb, int s, int m, int prec, int flags
   if (flags & SS_KEEP_FACTORS) {
     ws_request(h, kSlotFact, c * b * (size_t)nb * ss2);
     ws_request(h, kSlotFactPerm, i4 * b * (size_t)nb * S);
+    if (lu_panel_width(s) == 32) ws_request(h, kSlotFactInv, c * b * (size_t)nb * (size_t)lu_inverse_elems(s, 32));
   }
   ws_request(h, kSlotLuInv, lu_inverse_bytes(2 * b, s));
   // ss_apply_obc: the corner systems [R | C Q b' | I] of order 2s

@@ -89,6 +89,7 @@ enum Slot {
   kSlotLuInv,      // inverses of the LU's diagonal blocks (triangular-solve leaves)
   kSlotSpike,      // partition tables, the second column buffer and the interface systems of the merges
   kSlotCpl,        // FP32 coupling blocks of the next recursion step (BF16-term products)
+  kSlotFactInv,    // kept inverses of the diagonal blocks of the kept factorizations (32-column panels)
   kNumSlots
 };
 
@@ -104,6 +105,7 @@ struct ss_ctx {
   int lu_width = 0;          // LU panel width to use where valid for the order (0: the default)
   // what the kept workspaces currently describe (for ss_refine_psi)
   bool fact_valid = false;   // kSlotX + kSlotFact/FactPerm hold a first-column recursion
+  bool fact_inv = false;     // and kSlotFactInv the inverses of their 32 x 32 diagonal blocks
   int fact_batch = 0, fact_nb = 0, fact_s = 0;
   double fact_absorb = 0.0;  // absorbing shift of the boundary blocks the kept factors were formed with
   bool corner_valid = false;  // kSlotM/kSlotPerm hold the factored corner systems of ss_apply_obc

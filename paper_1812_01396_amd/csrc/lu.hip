@@ -943,6 +943,16 @@ __global__ void k_copy_out(LuArgs a) {
 using NarrowTile = TileCfg<32, 32, 32, 2, 2>;
 constexpr int kTrsmBlock = 256;
 
+// the staged right-hand sides of k_trsm_block as the right operand of a product: element (k, c)
+struct LdLds {
+  const double *re, *im;
+  int pitch;
+  static constexpr bool kFastSecond = true;
+  __device__ __forceinline__ double2 operator()(int k, int c) const {
+    return make_double2(re[k * pitch + c], im[k * pitch + c]);
+  }
+};
+
 template <bool kUpper>
 __global__ void __launch_bounds__(NarrowTile::NT) k_trsm_block(LuArgs a, int r0, int rows, int c_lo, int c_hi) {
   using T = NarrowTile;
@@ -980,19 +990,31 @@ __global__ void __launch_bounds__(NarrowTile::NT) k_trsm_block(LuArgs a, int r0,
       cr[r * CP + c] = b.x;
       ci[r * CP + c] = b.y;
     });
-    for (int idx = threadIdx.x; idx < P * P; idx += T::NT) {
-      const int i = idx / P, j = idx % P;
-      const bool in = i < w && j < w && (kUpper ? j > i : j < i);
-      st2(tri[i][j], in ? M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + j] : make_double2(0.0, 0.0));
-      if (kUpper && j == i)
-        st2(rdiag[i], i < w ? crecip(M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + i]) : make_double2(0.0, 0.0));
+    if (a.inv != nullptr) {
+      // the kept inverse of the panel's diagonal block times the staged rows, on the matrix cores
+      __syncthreads();
+      const double2 *tinv = a.inv + (long)mat * a.sInv + ((long)((r0 + p0) / P) * 2 + (kUpper ? 1 : 0)) * P * P;
+      Acc<T> acc2;
+      acc2.zero();
+      mma_loop<T>(LdRow{tinv, P}, LdLds{cr, ci, CP}, 0, w, 0, cw, 0, w, acc2, lds);
+      acc_foreach<T>(acc2, [&](int r, int c, double2 x) {
+        if (r < w && c < cw) cv.p[(long)sperm[p0 + r] * cv.ld + c0 + c] = x;
+      });
+    } else {
+      for (int idx = threadIdx.x; idx < P * P; idx += T::NT) {
+        const int i = idx / P, j = idx % P;
+        const bool in = i < w && j < w && (kUpper ? j > i : j < i);
+        st2(tri[i][j], in ? M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + j] : make_double2(0.0, 0.0));
+        if (kUpper && j == i)
+          st2(rdiag[i], i < w ? crecip(M[(long)sperm[p0 + i] * a.ldm + r0 + p0 + i]) : make_double2(0.0, 0.0));
+      }
+      __syncthreads();
+      tile_trsm<P, kUpper>(
+          [&](int i, int col) { return col < P ? make_double2(cr[i * CP + col], ci[i * CP + col]) : make_double2(0.0, 0.0); },
+          tri, rdiag, w, [&](int i, int col, double2 x) {
+            if (col < cw) cv.p[(long)sperm[p0 + i] * cv.ld + c0 + col] = x;
+          });
     }
-    __syncthreads();
-    tile_trsm<P, kUpper>(
-        [&](int i, int col) { return col < P ? make_double2(cr[i * CP + col], ci[i * CP + col]) : make_double2(0.0, 0.0); },
-        tri, rdiag, w, [&](int i, int col, double2 x) {
-          if (col < cw) cv.p[(long)sperm[p0 + i] * cv.ld + c0 + col] = x;
-        });
     __syncthreads();  // the panel's rows are stored before the next panel's product reads them
   }
 }
@@ -1180,6 +1202,9 @@ struct LuRun {
   }
 };
 
+int lu_width_of(ss_ctx *ctx, int n) { return panel_width(ctx, n); }
+long lu_inverse_elems(int n, int w) { return (long)cdiv(n, w) * 2 * w * w; }
+
 ss_status lu_solve(ss_ctx *ctx, const LuDesc &d) {
   if (d.nmat <= 0) return SS_OK;
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_solve: order out of range");
@@ -1198,7 +1223,14 @@ ss_status lu_apply(ss_ctx *ctx, const LuDesc &d) {
   if (d.n < 1 || d.n > kLuMaxN) return fail(ctx, SS_ERR_UNSUPPORTED, "lu_apply: order out of range");
   const int W = panel_width(ctx, d.n);
   if (d.nrhs <= 2 * NarrowTile::BN) {  // a few columns: diagonal blocks of kTrsmBlock rows, one launch each
-    if (W == 32) return LuRun<32, 1, 1024>{ctx, d, make_args(d)}.apply_narrow();
+    if (W == 32) {
+      LuArgs a = make_args(d);
+      if (d.inv != nullptr) {  // kept inverses of the 32 x 32 diagonal blocks
+        a.inv = const_cast<double2 *>(d.inv);
+        a.sInv = d.sInv;
+      }
+      return LuRun<32, 1, 1024>{ctx, d, a}.apply_narrow();
+    }
     if (W == 16) return LuRun<16, 1, 1024>{ctx, d, make_args(d)}.apply_narrow();
     return LuRun<8, 2, 1024>{ctx, d, make_args(d)}.apply_narrow();
   }

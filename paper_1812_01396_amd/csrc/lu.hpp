@@ -33,12 +33,21 @@ struct LuDesc {
   // products of the recursive factorization and of the triangular solves on the FP32 matrix cores
   // (operands rounded to FP32, FP32 accumulation, FP64 storage); panels, pivots and leaves stay FP64
   bool f32 = false;
+  // lu_apply only: inverses of the 32 x 32 diagonal blocks of L and U kept from the factorization's
+  // panels ([mat][panel][L, U][32][32], system stride sInv); with them (and 32-column panels) the block
+  // solves multiply by the inverses instead of substituting
+  const double2 *inv = nullptr;
+  long sInv = 0;
 };
 
 // Default panel width of the factorization for order n (32 up to n = 1024, 8 up to 2048); a context
 // may ask for another width (ss_ctx::lu_width) where lu_panel_width_ok allows it.
 int lu_panel_width(int n);
 bool lu_panel_width_ok(int n, int w);
+// The panel width the context's factorizations of order n use (its own width where valid, else the
+// default), and the doubles2 per system of the diagonal-block inverses they keep.
+int lu_width_of(ss_ctx *ctx, int n);
+long lu_inverse_elems(int n, int w);
 // Largest order supported.
 constexpr int kLuMaxN = 2048;
 

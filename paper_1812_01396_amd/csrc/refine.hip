@@ -342,6 +342,11 @@ ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, 
   dd.sX = (long)nb * sm;
   dd.ldx = m;
   dd.skip = a.done;
+  void *wFI = nullptr;
+  if (ctx->fact_inv) {  // the kept inverses of the 32 x 32 diagonal blocks, laid out like the factors
+    SS_TRY(workspace(ctx, kSlotFactInv, 0, &wFI));
+    dd.sInv = (long)nb * lu_inverse_elems(s, 32);
+  }
   // the corner solve with R
   LuDesc dc;
   dc.nmat = batch;
@@ -381,6 +386,7 @@ ss_status refine_psi(ss_ctx *ctx, const ss_btd *hs, int batch, const int *kidx, 
       const int t = nb - 1 - i;
       dd.M = (double2 *)wF + (long)t * ss2;
       dd.perm = (int *)wP + (long)t * s;
+      if (ctx->fact_inv) dd.inv = (const double2 *)wFI + (long)t * lu_inverse_elems(s, 32);
       dd.B = a.r + (long)i * sm;
       dd.X = a.g + (long)i * sm;
       SS_TRY(lu_apply(ctx, dd));

@@ -321,8 +321,9 @@ __global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_
 }
 
 // Keep the factorization of the first-column recursion's step t (L\U in physical rows and the row
-// map) for later solves with the same diagonal systems.
-__global__ void k_save_factors(SweepArgs a, double2 *F, int *P, int t) {
+// map, and, when inv is given, its panels' inverses of their 32 x 32 diagonal blocks: sInv per system)
+// for later solves with the same diagonal systems.
+__global__ void k_save_factors(SweepArgs a, double2 *F, int *P, int t, const double2 *inv, long sInv, double2 *FI) {
   const int inst = blockIdx.y, s = a.s;
   if (t >= nb_of(a, inst)) return;
   const long ss2 = (long)s * s;
@@ -332,6 +333,12 @@ __global__ void k_save_factors(SweepArgs a, double2 *F, int *P, int t) {
   for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < ss2; idx += (long)gridDim.x * blockDim.x) {
     const int r = idx / s, c = idx % s;
     f[idx] = M[(long)r * 2 * s + c];
+  }
+  if (inv != nullptr) {
+    const double2 *src = inv + (long)(2 * inst) * sInv;
+    double2 *dst = FI + blk_t * sInv;
+    for (long idx = blockIdx.x * (long)blockDim.x + threadIdx.x; idx < sInv; idx += (long)gridDim.x * blockDim.x)
+      dst[idx] = src[idx];
   }
   if (blockIdx.x == 0)
     for (int r = threadIdx.x; r < s; r += blockDim.x) P[blk_t * s + r] = a.perm[(long)(2 * inst) * s + r];
@@ -376,11 +383,16 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
   d.ldx = s;
   d.f32 = prec == SS_PREC_FP32_LU;
 
-  double2 *F = nullptr;
+  double2 *F = nullptr, *FI = nullptr;
   int *P = nullptr;
+  // with 32-column panels the kept factors also keep their panels' diagonal-block inverses
+  const bool keep_inv = keep && lu_width_of(ctx, n) == 32;
+  const long sInv = lu_inverse_elems(n, 32);
   if (keep) {
     SS_TRY(workspace(ctx, kSlotFact, sizeof(double2) * (size_t)total_blocks * ss2, (void **)&F));
     SS_TRY(workspace(ctx, kSlotFactPerm, sizeof(int) * (size_t)total_blocks * s, (void **)&P));
+    if (keep_inv)
+      SS_TRY(workspace(ctx, kSlotFactInv, sizeof(double2) * (size_t)total_blocks * sInv, (void **)&FI));
   }
   ctx->fact_valid = false;
   const bool f32 = prec == SS_PREC_FP32 || prec == SS_PREC_FP32_LU;
@@ -403,9 +415,12 @@ static ss_status sweep_run(ss_ctx *ctx, SweepArgs &a, const std::vector<int> &ac
     d.nmat = 2 * na;
     d.X = a.X + (long)t * ss2;
     SS_TRY(lu_solve(ctx, d));
-    if (keep)
+    if (keep) {
+      double2 *inv = nullptr;  // the inverses this step's factorization left in the LU's workspace
+      if (keep_inv) SS_TRY(workspace(ctx, kSlotLuInv, sizeof(double2) * (size_t)d.nmat * sInv, (void **)&inv));
       hipLaunchKernelGGL(k_save_factors, dim3(std::min(cdiv((int)std::min<long>(ss2, 1 << 30), 256), 64), na),
-                         dim3(256), 0, ctx->stream, a, F, P, t);
+                         dim3(256), 0, ctx->stream, a, F, P, t, (const double2 *)inv, sInv, FI);
+    }
   }
   hipLaunchKernelGGL(k_sweep_finish, dim3(cdiv(batch, 256)), dim3(256), 0, ctx->stream, a);
   for (int u = 0; u < nsteps; ++u) {
@@ -449,6 +464,7 @@ ss_status precompute_columns(ss_ctx *ctx, const ss_btd *hs, int batch, const int
   SS_TRY(sweep_run(ctx, a, std::vector<int>(nb, batch), (long)batch * nb, nullptr, prec, keep));
   if (keep) {
     ctx->fact_valid = true;
+    ctx->fact_inv = lu_width_of(ctx, s) == 32;
     ctx->fact_batch = batch;
     ctx->fact_nb = nb;
     ctx->fact_s = s;
