@@ -904,7 +904,7 @@ def run_spike(args):
     print(json.dumps(out))
 
 
-def compare_precisions(workload: str, steps: int = 1, warmup: int = 1):
+def compare_precisions(workload: str, steps: int = 1, warmup: int = 1, modes=("fp64", "mixed", "mixed-bf16")):
     """One timed step of `workload` in plain FP64 and in the two mixed forms (the block formations and the
     chain with FP32 products, or with BF16-term products on the BF16 matrix cores; FP64 refinement of
     psi, T from the refined psi with the broadening tail), each after `warmup` untimed steps: solves/s and
@@ -915,7 +915,7 @@ def compare_precisions(workload: str, steps: int = 1, warmup: int = 1):
     import torch
 
     res = {}
-    for mode in ("fp64", "mixed", "mixed-bf16"):
+    for mode in modes:
         print(f"{workload} {mode}: building the pipeline", file=sys.stderr, flush=True)
         pipe = Pipeline(workload, mode=mode)
         for _ in range(warmup):
@@ -1158,7 +1158,8 @@ def main():
         "device_mem_used_gib": round((torch.cuda.mem_get_info()[1] - torch.cuda.mem_get_info()[0]) / 2**30, 1),
     }
     if args.compare_precisions and args.workload == "dft512" and args.mode == "fp64":
-        # release this workload's device memory, then the s = 1024 workload in both precisions
+        # release this workload's device memory, then the s = 1024 workload in the three precisions and this
+        # workload in the BF16-mixed form
         pipe.ctx.close()
         pipe.ctx_s.close()
         for k in list(vars(pipe)):
@@ -1171,6 +1172,10 @@ def main():
             out["precision_comparison"] = compare_precisions("dft1024")
         except Exception as e:  # reported, never fatal for the headline line
             out["precision_comparison"] = {"error": f"{type(e).__name__}: {e}"}
+        try:  # the mixed form of this same workload, against the plain FP64 headline above
+            out["mixed_same_workload"] = compare_precisions("dft512", steps=args.steps, modes=("mixed-bf16",))
+        except Exception as e:
+            out["mixed_same_workload"] = {"error": f"{type(e).__name__}: {e}"}
     print(json.dumps(out))
 
 
