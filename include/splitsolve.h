@@ -163,7 +163,10 @@ ss_status ss_lead_selfenergy(ss_ctx *ctx, int batch, int s, int nk, const ss_c12
 
 /* flags of ss_precompute_columns */
 #define SS_KEEP_FACTORS 1 /* keep the first-column recursion's factors in the context for     */
-                          /* ss_refine_psi (valid until the next ss_precompute_columns call)    */
+                          /* ss_refine_psi (valid until the next ss_precompute_columns call):   */
+                          /* per block the LU (16 s^2 bytes) and row map, and with 32-column    */
+                          /* panels their diagonal-block inverses (1024 s bytes), with which    */
+                          /* the refinement's block solves run as matrix-core products          */
 
 /* Step 1 (Sec. 3B, Alg. 1): Q = [A^{-1}_{:,1}, A^{-1}_{:,n_B}] for A = E*S - H.
  *
