@@ -650,7 +650,7 @@ class Pipeline:
     """
 
     def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-10,
-                 accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0):
+                 accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0, lanes: int = 1):
         import torch
 
         import paper_1812_01396_amd as ss
@@ -671,8 +671,11 @@ class Pipeline:
         self.absorb = w["absorb"]
         self.w, self.insts, self.E_np, self.kidx_np, self.inj_np = w, insts, E_np, kidx_np, inj_np
         s, nb, m = w["s"], w["nb"], w["m"]
-        self.chunk = chunk or w["chunk"]
         self.n = nb_inst = len(E_np)
+        # lanes > 1: the instances split into that many lanes, each with a context, stream and host thread
+        # of its own running its whole path (Step 1, corner, refinement, T) beside the others
+        self.lanes = max(1, int(lanes))
+        self.chunk = -(-nb_inst // self.lanes) if self.lanes > 1 else (chunk or w["chunk"])
         dev = self.dev = torch.device("cuda", 0)
 
         def t(a, dt=torch.complex128):
@@ -708,11 +711,24 @@ class Pipeline:
         self.stream_sig = torch.cuda.Stream(dev)  # default priority
         self.ctx = ss.Context(0, self.stream_main)
         self.ctx_s = ss.Context(0, self.stream_sig)
+        self.lane_streams, self.lane_ctx, self.lane_Q = [self.stream_main], [self.ctx], [self.Qbuf]
+        for _ in range(1, self.lanes):
+            st = torch.cuda.Stream(dev)  # default priority
+            self.lane_streams.append(st)
+            self.lane_ctx.append(ss.Context(0, st))
+            self.lane_Q.append(torch.empty(self.chunk, nb, s, 2 * s, dtype=c128, device=dev))
         ss.splitsolve._check_kidx(self.kidx, len(insts))  # once: the step itself never reads back to the host
+
+    def close(self):
+        """Release the pipeline's contexts (their device workspaces); the tensors go with the object."""
+        for c in self.lane_ctx + [self.ctx_s]:
+            c.close()
 
     def run(self, recursion_ms=None):
         """One step.  recursion_ms: a list that receives the summed duration (ms) of the recursion's
         kernels of each chunk (HIP events on the main stream; synchronizes after each chunk's recursion)."""
+        if self.lanes > 1:
+            return self._run_lanes(recursion_ms)
         ss, torch, w = self.ss, self.torch, self.w
         # the previous step's readers of sigma (main stream) finish before sigma is overwritten
         prev = torch.cuda.Event()
@@ -820,10 +836,98 @@ class Pipeline:
                     frac_fp64_peak=round(flops / (ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
                     current_spread_max=spread, integrated_density_sum=float(n_int.sum().item()))
 
-    def _fp64_fallback(self, c0, c1):
+    def _run_lanes(self, recursion_ms=None):
+        """One step with the instances split into lanes: the self-energies of all instances on their own
+        stream as in run(), and every lane's Step 1, corner correction, refinement and T on its own context
+        and stream from a host thread of its own (the refinement's convergence polls wait for that lane's
+        stream only), so one lane's latency-bound tail overlaps the other lanes' work.  recursion_ms receives
+        the summed duration of lane 0's recursion kernels (self.chunk instances)."""
+        ss, torch, w = self.ss, self.torch, self.w
+        prevs = []
+        for st in self.lane_streams:  # the previous step's readers of sigma finish before it is overwritten
+            e = torch.cuda.Event()
+            e.record(st)
+            prevs.append(e)
+        done = torch.cuda.Event()
+        sig_ready = threading.Event()
+        err = []
+
+        def run_sigma():
+            try:
+                with torch.cuda.stream(self.stream_sig):
+                    for e in prevs:
+                        self.stream_sig.wait_event(e)
+                    ss.ss_lead_selfenergy(self.ctx_s, *self.lead, self.E, w["eta"], kidx=self.kidx, sigma=self.sigma,
+                                          iters=self.iters, resid=self.resid, info=self.info_s, validate=False)
+                    done.record(self.stream_sig)
+            except Exception as e:  # surfaced after join
+                err.append(e)
+            finally:
+                sig_ready.set()
+
+        def run_lane(li):
+            try:
+                c0 = li * self.chunk
+                c1 = min(c0 + self.chunk, self.n)
+                if c0 >= c1:
+                    return
+                ctx, st, q = self.lane_ctx[li], self.lane_streams[li], self.lane_Q[li][: c1 - c0]
+                with torch.cuda.stream(st):
+                    self._path(ctx, q, c0, c1, sig_ready, done, err, recursion_ms if li == 0 else None)
+            except Exception as e:
+                err.append(e)
+
+        ths = [threading.Thread(target=run_sigma)] + [threading.Thread(target=run_lane, args=(li,))
+                                                       for li in range(self.lanes)]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        if err:
+            raise err[0]
+        for st in self.lane_streams[1:]:  # later work on the main stream follows every lane
+            e = torch.cuda.Event()
+            e.record(st)
+            self.stream_main.wait_event(e)
+
+    def _path(self, ctx, q, c0, c1, sig_ready, done, err, recursion_ms=None):
+        """Step 1 and the post-processing of instances [c0, c1) on ctx (and the current stream, ctx's)."""
+        ss, w = self.ss, self.w
+        mixed = self.mode != "fp64"
+        if recursion_ms is not None:
+            ctx.kernel_timer(RECURSION_FAMILIES)
+        ss.ss_precompute_columns(ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1], kidx=self.kidx[c0:c1], Q=q,
+                                 info=self.info_q[c0:c1], validate=False, prec=self.prec, keep_factors=mixed,
+                                 absorb=self.absorb)
+        if recursion_ms is not None:
+            recursion_ms.append(ctx.kernel_timer_read()[0])
+            ctx.kernel_timer(None)
+        sig_ready.wait()
+        if err:
+            return
+        self.torch.cuda.current_stream().wait_event(done)
+        sig = self.sigma[c0:c1]
+        if mixed:
+            ss.ss_injection_left(ctx, sig, w["m"], inj=self.inj[c0:c1], rank=self.rank[c0:c1])
+        ss.ss_apply_obc(ctx, q, sig, inj=self.inj[c0:c1], psi=self.psi[c0:c1], gc=self.gc[c0:c1],
+                        info=self.info_o[c0:c1], absorb=self.absorb)
+        if mixed:
+            self.psi0[c0:c1].copy_(self.psi[c0:c1, -1])
+            ss.ss_refine_psi(ctx, self.Hd, self.Hu, self.Sd, self.Su, self.E[c0:c1], q, sig, self.inj[c0:c1],
+                             self.psi[c0:c1], kidx=self.kidx[c0:c1], tol=self.refine_tol,
+                             iters=self.ir_iters[c0:c1], resid=self.ir_resid[c0:c1])
+            self._fp64_fallback(c0, c1, ctx, q)
+            ss.ss_transmission_psi(ctx, self.psi[c0:c1], sig, T=self.T_psi[c0:c1], psi0=self.psi0[c0:c1],
+                                   gc=self.gc[c0:c1])
+        else:
+            ss.ss_transmission(ctx, self.gc[c0:c1], sig, T=self.T[c0:c1])
+
+    def _fp64_fallback(self, c0, c1, ctx=None, qbuf=None):
         """Instances whose refinement from the FP32-product factors did not reach the tolerance (pivot
         blocks too ill-conditioned for FP32 products) are solved again with FP64 products and refined."""
         ss, torch = self.ss, self.torch
+        ctx = ctx if ctx is not None else self.ctx
+        qbuf = qbuf if qbuf is not None else self.Qbuf
         bad = torch.nonzero(~(self.ir_resid[c0:c1] <= self.accept_tol)).flatten()
         nbad = int(bad.numel())  # one host read per chunk
         self.fallback += nbad
@@ -832,16 +936,16 @@ class Pipeline:
         idx = bad + c0
         E_b, k_b = self.E[idx].contiguous(), self.kidx[idx].contiguous()
         sig_b, inj_b = self.sigma[idx].contiguous(), self.inj[idx].contiguous()
-        q = self.Qbuf[:nbad]
+        q = qbuf[:nbad]
         info_b = torch.zeros(nbad, dtype=torch.int32, device=self.dev)
-        ss.ss_precompute_columns(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, E_b, kidx=k_b, Q=q, info=info_b,
+        ss.ss_precompute_columns(ctx, self.Hd, self.Hu, self.Sd, self.Su, E_b, kidx=k_b, Q=q, info=info_b,
                                  validate=False, prec=ss.SS_PREC_FP64, keep_factors=True, absorb=self.absorb)
         self.info_q[idx] = info_b
-        psi_b, gc_b, info_ob = ss.ss_apply_obc(self.ctx, q, sig_b, inj=inj_b, absorb=self.absorb)
+        psi_b, gc_b, info_ob = ss.ss_apply_obc(ctx, q, sig_b, inj=inj_b, absorb=self.absorb)
         self.psi0[idx] = psi_b[:, -1]
         it_b = torch.zeros(nbad, dtype=torch.int32, device=self.dev)
         res_b = torch.zeros(nbad, dtype=torch.float64, device=self.dev)
-        ss.ss_refine_psi(self.ctx, self.Hd, self.Hu, self.Sd, self.Su, E_b, q, sig_b, inj_b, psi_b, kidx=k_b,
+        ss.ss_refine_psi(ctx, self.Hd, self.Hu, self.Sd, self.Su, E_b, q, sig_b, inj_b, psi_b, kidx=k_b,
                          tol=self.refine_tol, iters=it_b, resid=res_b)
         self.psi[idx] = psi_b
         self.gc[idx] = gc_b  # the Caroli T of these instances also comes from the FP64 factors
@@ -934,8 +1038,7 @@ def compare_precisions(workload: str, steps: int = 1, warmup: int = 1, modes=("f
             rec.update(refine_iters=[int(it.min()), int(it.max())],
                        refine_resid_max=float(pipe.ir_resid.max().item()), fp64_fallback=pipe.fallback)
         res[mode] = rec
-        pipe.ctx.close()
-        pipe.ctx_s.close()
+        pipe.close()
         for k in list(vars(pipe)):
             setattr(pipe, k, None)
         del pipe
@@ -962,6 +1065,9 @@ def main():
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
+    ap.add_argument("--lanes", type=int, default=1,
+                    help="split the instances into this many lanes, each with its own context, stream and host "
+                         "thread (the refinement's latency-bound tail of one lane overlaps the others' work)")
     ap.add_argument("--refine-tol", type=float, default=1e-10, help="mixed: relative residual the refinement stops at")
     ap.add_argument("--m-inj", type=int, default=0, help="mixed: columns of the injection factor (0: workload's m)")
     ap.add_argument("--roofline-kernel", default="lu_gemm",
@@ -1038,7 +1144,7 @@ def main():
     if args.workload == "learned":
         return run_learned(args)
     pipe = Pipeline(args.workload, args.chunk, args.mode, absorb=None if args.absorb < 0 else args.absorb,
-                    refine_tol=args.refine_tol, m=args.m_inj)
+                    refine_tol=args.refine_tol, m=args.m_inj, lanes=args.lanes)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel
     timed_ctx = pipe.ctx_s if fam in ("dec_update",) else pipe.ctx
@@ -1069,6 +1175,7 @@ def main():
                 fam_alone = (a_ms, a_n, a_flops)
         obs = pipe.observables()
 
+    rec_inst = min(pipe.chunk, nbatch) if pipe.lanes > 1 else nbatch
     it_np = pipe.iters.cpu().numpy().astype(np.float64)
     mixed = args.mode != "fp64"
     # the product's T: Caroli (T_LR, T_RL) in fp64 mode; T carried by the refined psi in mixed mode
@@ -1125,7 +1232,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "s": s, "nb": nb, "instances": nbatch, "energies": w["n_e"],
                    "k_points": len(w["ks"]), "m_inj": m, "eta": w["eta"], "chunk": pipe.chunk,
-                   "precision": args.mode, "absorb": pipe.absorb},
+                   "precision": args.mode, "absorb": pipe.absorb, "lanes": pipe.lanes},
         "tflops_step": round(f_step / (ms_per_step * 1e-3) / 1e12, 3),
         "frac_fp64_peak_step": round(f_step / (ms_per_step * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4),
         "decimation_iters": [int(it_np.min()), int(it_np.max()), round(float(it_np.mean()), 2)],
@@ -1143,8 +1250,10 @@ def main():
         # step, measured with HIP events while the self-energies run beside it on the second stream
         "observables": obs,
         "recursion": None if args.no_extra else dict(kernel_ms=round(sum(rec_ms), 2),
-                          tflops=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
-                          frac_peak=round(nbatch * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /
+                          # with lanes, the timed recursion is lane 0's (pipe.chunk instances)
+                          instances_timed=rec_inst,
+                          tflops=round(rec_inst * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12, 3),
+                          frac_peak=round(rec_inst * sweep_flops(nb, s) / (sum(rec_ms) * 1e-3) / 1e12 /
                                           (FP32_PEAK_TFLOPS if mixed else FP64_PEAK_TFLOPS), 4),
                           # Step 1 run by itself after the timed steps (nothing beside it on the chip)
                           alone_wall_ms=round(rec_alone_wall, 2), alone_kernel_ms=round(rec_alone_kms, 2),
@@ -1160,8 +1269,7 @@ def main():
     if args.compare_precisions and args.workload == "dft512" and args.mode == "fp64":
         # release this workload's device memory, then the s = 1024 workload in the three precisions and this
         # workload in the BF16-mixed form
-        pipe.ctx.close()
-        pipe.ctx_s.close()
+        pipe.close()
         for k in list(vars(pipe)):
             setattr(pipe, k, None)
         del pipe

@@ -34,8 +34,7 @@ def dft512():
     pipe.run()
     torch.cuda.synchronize()
     yield pipe
-    pipe.ctx.close()
-    pipe.ctx_s.close()
+    pipe.close()
     for k in list(vars(pipe)):  # drop the device tensors now: the next full-size module needs the memory
         setattr(pipe, k, None)
     gc.collect()
@@ -85,8 +84,15 @@ def test_dft512_sampled_vs_oracle(dft512, b):
     print(f"dft512 oracle for instance {b}", flush=True)
     inst = p.insts[p.kidx_np[b]]
     E = float(p.E_np[b])
+    # Q stays in its chunk buffer: every lane's when the instances run in lanes (one chunk each), else only
+    # the last chunk's
+    if p.lanes > 1:
+        li = b // p.chunk
+        q_dev = p.lane_Q[li][b - li * p.chunk]
+    else:
+        q_dev = p.Qbuf[b - (p.n - p.chunk)] if b >= p.n - p.chunk else None
     ref = transport.solve_instance(inst.Hd, inst.Hu, inst.Sd, inst.Su, inst.H00, inst.H01, inst.S00, inst.S01,
-                                   E, w["eta"], inj=p.inj_np[b], want_q=(b >= p.n - p.chunk))
+                                   E, w["eta"], inj=p.inj_np[b], want_q=q_dev is not None)
     a0, a1, am1 = selfenergy.lead_blocks(inst.H00, inst.H01, inst.S00, inst.S01, E, w["eta"])
     tol = max(1e-10, 10 * UNIT * selfenergy.decimation_conditioning(a0, a1, am1))
     sig = p.sigma[b].cpu().numpy()
@@ -97,8 +103,8 @@ def test_dft512_sampled_vs_oracle(dft512, b):
     T = p.T[b].cpu().numpy()
     assert abs(T[0] - ref["t_lr"]) <= 1e-8 * max(1.0, ref["t_lr"])
     assert abs(T[1] - ref["t_rl"]) <= 1e-8 * max(1.0, ref["t_rl"])
-    if ref["q"] is not None:  # Q of the last chunk is still in the chunk buffer
-        q = p.Qbuf[b - (p.n - p.chunk)].cpu().numpy()
+    if q_dev is not None:
+        q = q_dev.cpu().numpy()
         # Q of the absorbing split: the first and last block columns of A' = A + i*absorb*[boundary blocks]
         ad, au, al = transport.device_blocks(inst.Hd, inst.Hu, inst.Sd, inst.Su, E)
         ad = ad.copy()
@@ -110,15 +116,18 @@ def test_dft512_sampled_vs_oracle(dft512, b):
         assert _rel(q, q_ref) <= max(1e-10, 10 * spread)
 
 
-def test_chain16_pipeline_matches_channel_counts():
+@pytest.mark.parametrize("mode,lanes", [("fp64", 1), ("fp64", 2), ("mixed-bf16", 2)])
+def test_chain16_pipeline_matches_channel_counts(mode, lanes):
+    """The pipeline in one chunk, and in two lanes (contexts, streams and host threads of their own, the
+    refinement's convergence polls waiting on one lane only), against the stored channel counts."""
     import bench
     rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "chain16_channels.txt"), comments="#")
-    pipe = bench.Pipeline("chain16")
-    pipe.run()
+    pipe = bench.Pipeline("chain16", mode=mode, lanes=lanes)
+    for _ in range(2):  # the second step reuses every workspace and event
+        pipe.run()
     torch.cuda.synchronize()
     assert np.allclose(pipe.E_np, rows[:, 0])
-    T = pipe.T.cpu().numpy()
+    T = pipe.T.cpu().numpy() if mode == "fp64" else np.stack([pipe.T_psi.cpu().numpy()] * 2, axis=1)
     assert np.abs(T[:, 0] - rows[:, 1]).max() <= 1e-8
     assert np.abs(T[:, 1] - rows[:, 1]).max() <= 1e-8
-    pipe.ctx.close()
-    pipe.ctx_s.close()
+    pipe.close()

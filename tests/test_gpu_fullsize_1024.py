@@ -1,7 +1,8 @@
 """Full-size parity of the s = 1024 workload (nb = 60, N = 61440, 32 energies at k = pi/3) in the
 benchmark's own launch configuration (bench.Pipeline, all 32 instances in one chunk), in plain FP64 and
-in the mixed-precision form (FP32 products in the recursion and in the LU's blocked updates, FP64
-panels, FP64 refinement of psi on the open system, T from the refined psi with the broadening tail).
+in the two mixed-precision forms (the block formations and the chain with FP32 products, or with
+split-BF16 products on the BF16 matrix cores; the LU, panels and corner in FP64; FP64 refinement of psi
+on the open system, T from the refined psi with the broadening tail).
 
 Every instance's T is compared with the oracle's Caroli pair stored in tests/golden/dft1024_transmission.txt
 (written by tests/golden/make_golden_slab.py from the oracle alone) at 1e-8.  The device is a perfect
@@ -28,8 +29,7 @@ def _run(mode):
     out = dict(T=pipe.T.cpu().numpy(), T_psi=pipe.T_psi.cpu().numpy(), E=pipe.E_np.copy(),
                info=[int((i != 0).sum()) for i in (pipe.info_s, pipe.info_q, pipe.info_o)],
                resid=pipe.ir_resid.cpu().numpy(), iters=pipe.ir_iters.cpu().numpy(), fallback=pipe.fallback)
-    pipe.ctx.close()
-    pipe.ctx_s.close()
+    pipe.close()
     for k in list(vars(pipe)):
         setattr(pipe, k, None)
     del pipe
@@ -52,8 +52,9 @@ def test_dft1024_fp64_all_instances():
     assert np.abs(T - ref[:, 6:7]).max() <= 1e-3
 
 
-def test_dft1024_mixed_all_instances():
-    out = _run("mixed")
+@pytest.mark.parametrize("mode", ["mixed", "mixed-bf16"])
+def test_dft1024_mixed_all_instances(mode):
+    out = _run(mode)
     assert out["info"] == [0, 0, 0]
     assert (out["resid"] <= 1e-10).all(), out["resid"].max()
     ref = np.loadtxt(GOLDEN, comments="#")
