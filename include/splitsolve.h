@@ -75,6 +75,9 @@ ss_status ss_set_sync_free(ss_ctx *ctx, int on);
  * Results agree to rounding for every width.  SS_ERR_ARG for any other value.  A plan sets the width of
  * each of its groups itself. */
 ss_status ss_set_lu_width(ss_ctx *ctx, int width);
+/* Tile of the LU's general block products on this context: 0 (default) 64 x 64, 1 32 x 64 (twice the
+ * workgroups per product, for batches too small to fill the chip).  SS_ERR_ARG for other values. */
+ss_status ss_set_lu_tile(ss_ctx *ctx, int tile);
 /* Block the host until the context's stream has drained. */
 ss_status ss_synchronize(ss_ctx *ctx);
 /* Static text for a status code, and the detail of the context's last failure ("" if none). */
@@ -378,7 +381,8 @@ ss_status ss_lead_selfenergy_warm(ss_ctx *ctx, int batch, int s, int nk, const s
  * work is captured once at creation, as a sequence of graph segments of about graph_segment_nodes
  * nodes each (cut at launch sites), and every ss_plan_execute replays each group's segments in order on
  * the group's stream (all groups forked from and joined into one origin stream).
- * With autotune, candidate LU panel widths and chunk sizes are timed per group at creation.
+ * With autotune, candidate LU panel widths, LU product tiles and chunk sizes are timed per group at
+ * creation.
  *
  * Instance blocks are device pointers owned by the caller and must stay valid and unmoved for the
  * plan's life (the plan and its graph keep the addresses; the values are read at every execution).
@@ -421,6 +425,8 @@ ss_status ss_plan_execute(ss_plan *plan);
 /* Groups of the plan (by block size) and, per group: s, instance count, chunk size, LU panel width,
  * and the autotuner's best probe time in ms (0 without autotune). */
 int ss_plan_groups(const ss_plan *plan);
+/* The LU product tile (as ss_set_lu_tile) a group of the plan uses; -1 for a bad group index. */
+int ss_plan_lu_tile(const ss_plan *plan, int group);
 ss_status ss_plan_describe(const ss_plan *plan, int group, int *s, int *count, int *chunk, int *lu_width,
                            double *tune_ms);
 /* Nodes of the captured group graphs, summed (0 without use_graph); a negative value -n means that a

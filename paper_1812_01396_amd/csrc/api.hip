@@ -185,6 +185,13 @@ ss_status ss_set_lu_width(ss_ctx *ctx, int width) {
   return SS_OK;
 }
 
+ss_status ss_set_lu_tile(ss_ctx *ctx, int tile) {
+  if (!ctx) return SS_ERR_ARG;
+  if (tile != 0 && tile != 1) return ss::fail(ctx, SS_ERR_ARG, "ss_set_lu_tile: tile must be 0 or 1");
+  ctx->lu_tile = tile;
+  return SS_OK;
+}
+
 ss_status ss_synchronize(ss_ctx *ctx) {
   SS_TRY(enter(ctx));
   if (hipStreamSynchronize(ctx->stream) != hipSuccess) return fail(ctx, SS_ERR_DEVICE, "stream synchronize failed");

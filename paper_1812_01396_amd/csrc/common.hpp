@@ -103,6 +103,7 @@ struct ss_ctx {
   int *host_word = nullptr;  // pinned word for convergence polls
   bool sync_free = false;    // never wait for the stream inside a call (stream/graph capture)
   int lu_width = 0;          // LU panel width to use where valid for the order (0: the default)
+  int lu_tile = 0;           // tile of the LU's general block products: 0 64 x 64, 1 32 x 64
   // what the kept workspaces currently describe (for ss_refine_psi)
   bool fact_valid = false;   // kSlotX + kSlotFact/FactPerm hold a first-column recursion
   bool fact_inv = false;     // and kSlotFactInv the inverses of their 32 x 32 diagonal blocks

@@ -577,6 +577,9 @@ using LuTileFlat = TileCfg<32, 128, 16, 1, 4>;
 // products of at most 32 columns (the depth-32 trailing updates inside a 64-column block): one column
 // of four waves, no padded half tile
 using LuTileNarrow = TileCfg<64, 32, 16, 4, 1>;
+// half-height tile for the general products (ss_ctx::lu_tile = 1): twice the workgroups per product,
+// for batches whose products are too few to fill the chip with 64 x 64 tiles
+using LuTileHalf = TileCfg<32, 64, 16, 2, 2>;
 
 // the row map into LDS (n <= kLuMaxN, 256 threads): all loads are issued before the first store
 __device__ __forceinline__ void load_perm(int *sperm, const int *perm, int n) {
@@ -1058,6 +1061,10 @@ struct LuRun {
       const int tiles = cdiv(r_hi - r_lo, LuTileNarrow::BM);
       hipLaunchKernelGGL(k_lu_gemm<LuTileNarrow>, dim3(tiles, d.nmat), dim3(LuTileNarrow::NT), 0, ctx->stream, a,
                          r_lo, r_hi, c_lo, c_hi, k_lo, k_hi);
+    } else if (ctx->lu_tile == 1) {
+      const int tiles = cdiv(r_hi - r_lo, LuTileHalf::BM) * cdiv(c_hi - c_lo, LuTileHalf::BN);
+      hipLaunchKernelGGL(k_lu_gemm<LuTileHalf>, dim3(tiles, d.nmat), dim3(LuTileHalf::NT), 0, ctx->stream, a, r_lo,
+                         r_hi, c_lo, c_hi, k_lo, k_hi);
     } else {
       const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);
       hipLaunchKernelGGL(k_lu_gemm<LuTile>, dim3(tiles, d.nmat), dim3(LuTile::NT), 0, ctx->stream, a, r_lo, r_hi,

@@ -40,7 +40,7 @@ struct Group {
   ss_ctx *ctx = nullptr;
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
-  int chunk = 0, lu_width = 0;
+  int chunk = 0, lu_width = 0, lu_tile = 0;
   double tune_ms = 0.0;
   std::vector<Chunk> chunks;
   void *tables = nullptr;  // one device allocation holding every chunk's tables
@@ -359,8 +359,8 @@ ss_status capture_groups(ss_plan *p) {
   return SS_OK;
 }
 
-// Time candidate (panel width, chunk size) pairs on the group's smallest instances and keep the pair
-// with the least time per recursion block.
+// Time candidate (panel width, product tile, chunk size) triples on the group's smallest instances and
+// keep the one with the least time per recursion block.
 ss_status autotune(ss_plan *p, Group &g, int chunk_max) {
   std::vector<int> widths;
   for (int w : {32, 16, 8})
@@ -371,26 +371,31 @@ ss_status autotune(ss_plan *p, Group &g, int chunk_max) {
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
     return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: event creation failed");
   double best = 1e300;
-  int best_w = widths[0], best_c = chunk_max;
+  int best_w = widths[0], best_c = chunk_max, best_t = 0;
   std::vector<int> full = g.order;
+  ss_status st = SS_OK;
   for (int c : chunks) {
     // probe batch: the c instances with the fewest blocks
     const int take = std::min<int>(c, (int)full.size());
     g.order.assign(full.end() - take, full.end());
-    ss_status st = build_chunks(p, g, take);
+    st = build_chunks(p, g, take);
     if (st != SS_OK) break;
     long blocks = 0;
     for (int idx : g.order) blocks += p->inst[idx].nb;
     for (int w : widths) {
-      g.ctx->lu_width = w;
-      // once untimed (workspaces grow, code loads), then timed
-      st = run_group(p, g);
-      if (st == SS_OK && hipEventRecord(e0, g.stream) == hipSuccess && (st = run_group(p, g)) == SS_OK &&
-          hipEventRecord(e1, g.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, e0, e1);
-        const double per = ms / std::max<long>(blocks, 1);
-        if (per < best) { best = per; best_w = w; best_c = c; g.tune_ms = ms; }
+      for (int tile : {0, 1}) {
+        g.ctx->lu_width = w;
+        g.ctx->lu_tile = tile;
+        // once untimed (workspaces grow, code loads), then timed
+        st = run_group(p, g);
+        if (st == SS_OK && hipEventRecord(e0, g.stream) == hipSuccess && (st = run_group(p, g)) == SS_OK &&
+            hipEventRecord(e1, g.stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess) {
+          float ms = 0.f;
+          (void)hipEventElapsedTime(&ms, e0, e1);
+          const double per = ms / std::max<long>(blocks, 1);
+          if (per < best) { best = per; best_w = w; best_c = c; best_t = tile; g.tune_ms = ms; }
+        }
+        if (st != SS_OK) break;
       }
       if (st != SS_OK) break;
     }
@@ -399,8 +404,11 @@ ss_status autotune(ss_plan *p, Group &g, int chunk_max) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   g.order = full;
+  if (st != SS_OK) return fail(p->ctx, st, "ss_plan: a tuning candidate failed: " + g.ctx->err);
   g.ctx->lu_width = best_w;
   g.lu_width = best_w;
+  g.ctx->lu_tile = best_t;
+  g.lu_tile = best_t;
   if (hipStreamSynchronize(g.stream) != hipSuccess) return fail(p->ctx, SS_ERR_DEVICE, "ss_plan: tuning failed");
   return build_chunks(p, g, best_c);
 }
@@ -562,6 +570,11 @@ ss_status ss_plan_describe(const ss_plan *p, int group, int *s, int *count, int 
 }
 
 int ss_plan_groups(const ss_plan *p) { return p ? (int)p->groups.size() : 0; }
+
+int ss_plan_lu_tile(const ss_plan *p, int group) {
+  if (!p || group < 0 || group >= (int)p->groups.size()) return -1;
+  return p->groups[group].lu_tile;
+}
 
 long long ss_plan_graph_nodes(const ss_plan *p) {
   if (!p) return 0;

@@ -22,11 +22,11 @@ SS_PREC_FP64, SS_PREC_FP32, SS_PREC_FP32_LU, SS_PREC_BF16 = 0, 1, 2, 3
 SS_KEEP_FACTORS = 1
 
 EXPORTS = (
-    "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_set_lu_width", "ss_synchronize", "ss_status_string", "ss_last_error",
+    "ss_create", "ss_destroy", "ss_set_stream", "ss_set_sync_free", "ss_set_lu_width", "ss_set_lu_tile", "ss_synchronize", "ss_status_string", "ss_last_error",
     "ss_workspace_bytes", "ss_workspace_size", "ss_kernel_timer", "ss_kernel_timer_read", "ss_measure_ceilings", "ss_lead_selfenergy",
     "ss_precompute_columns", "ss_lu_factor", "ss_apply_obc", "ss_transmission", "ss_transmission_noalloc",
     "ss_injection_left", "ss_refine_psi",
-    "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_describe",
+    "ss_transmission_psi", "ss_plan_create", "ss_plan_execute", "ss_plan_groups", "ss_plan_lu_tile", "ss_plan_describe",
     "ss_plan_graph_nodes", "ss_plan_graph_segments", "ss_plan_destroy", "ss_mlp_param_count", "ss_mlp_forward", "ss_mlp_backward",
     "ss_mlp_adam", "ss_warm_features", "ss_sigma_moments", "ss_sigma_encode", "ss_sigma_decode",
     "ss_lead_selfenergy_warm", "ss_observables", "ss_energy_integral", "ss_precompute_columns_spike",
@@ -89,6 +89,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_set_sync_free.restype = I
     lib.ss_set_lu_width.argtypes = [P, I]
     lib.ss_set_lu_width.restype = I
+    lib.ss_set_lu_tile.argtypes = [P, I]
+    lib.ss_set_lu_tile.restype = I
     lib.ss_synchronize.argtypes = [P]
     lib.ss_synchronize.restype = I
     lib.ss_status_string.argtypes = [I]
@@ -131,6 +133,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ss_plan_execute.restype = I
     lib.ss_plan_groups.argtypes = [P]
     lib.ss_plan_groups.restype = I
+    lib.ss_plan_lu_tile.argtypes = [P, I]
+    lib.ss_plan_lu_tile.restype = I
     lib.ss_plan_describe.argtypes = [P, I, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I),
                                      ctypes.POINTER(I), ctypes.POINTER(D)]
     lib.ss_plan_describe.restype = I
@@ -234,6 +238,10 @@ class Context:
     def set_lu_width(self, width: int):
         """LU panel width for this context's factorizations (0: the default by order)."""
         self.check(self.lib.ss_set_lu_width(self.handle, int(width)))
+
+    def set_lu_tile(self, tile: int):
+        """Tile of the LU's general block products for this context: 0 64 x 64 (default), 1 32 x 64."""
+        self.check(self.lib.ss_set_lu_tile(self.handle, int(tile)))
 
     def synchronize(self):
         self.check(self.lib.ss_synchronize(self.handle))
@@ -525,7 +533,7 @@ class Plan:
         return int(self.ctx.lib.ss_plan_graph_segments(self.handle))
 
     def groups(self):
-        """Per group: dict(s, count, chunk, lu_width, tune_ms)."""
+        """Per group: dict(s, count, chunk, lu_width, lu_tile, tune_ms)."""
         out = []
         lib = self.ctx.lib
         for g in range(lib.ss_plan_groups(self.handle)):
@@ -533,7 +541,8 @@ class Plan:
             ms = ctypes.c_double()
             self.ctx.check(lib.ss_plan_describe(self.handle, g, ctypes.byref(s), ctypes.byref(c), ctypes.byref(ch),
                                                 ctypes.byref(w), ctypes.byref(ms)))
-            out.append(dict(s=s.value, count=c.value, chunk=ch.value, lu_width=w.value, tune_ms=ms.value))
+            out.append(dict(s=s.value, count=c.value, chunk=ch.value, lu_width=w.value,
+                            lu_tile=int(lib.ss_plan_lu_tile(self.handle, g)), tune_ms=ms.value))
         return out
 
     def close(self):

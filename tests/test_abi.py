@@ -59,6 +59,8 @@ def test_null_arguments_are_rejected_without_a_device(lib):
     assert lib.ss_plan_create(None, 1, None, None, None, None, None) == 1
     assert lib.ss_plan_execute(None) == 1
     assert lib.ss_plan_groups(None) == 0
+    assert lib.ss_plan_lu_tile(None, 0) == -1
+    assert lib.ss_set_lu_tile(None, 0) == 1
     assert lib.ss_plan_graph_nodes(None) == 0
     assert lib.ss_plan_graph_segments(None) == 0
     assert lib.ss_plan_describe(None, 0, None, None, None, None, None) == 1

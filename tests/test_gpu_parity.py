@@ -244,6 +244,31 @@ def test_lu_factor_panel_widths(ctx, width, n):
         assert np.abs(lu[b] - ref).max() <= 1e-11 * np.abs(ref).max(), (b, np.abs(lu[b] - ref).max())
 
 
+@pytest.mark.parametrize("n", [100, 512, 1100])
+def test_lu_factor_half_tile(ctx, n):
+    """The 32 x 64 product tile (ss_set_lu_tile(1), an autotuner choice for small batches) gives the
+    oracle's pivots and factors, as the 64 x 64 tile does; other tile codes are argument errors."""
+    import paper_1812_01396_amd as ss
+    print(f"lu_factor tile=1 n={n}", flush=True)
+    rng = np.random.default_rng(7000 + n)
+    a = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
+    ctx.set_lu_tile(1)
+    try:
+        lu, perm, info = ss.ss_lu_factor(ctx, _dev(a))
+        torch.cuda.synchronize()
+    finally:
+        ctx.set_lu_tile(0)
+    lu, perm, info = lu.cpu().numpy(), perm.cpu().numpy(), info.cpu().numpy()
+    for b in range(2):
+        ref, rperm, rinfo = linalg.lu_partial_pivot(a[b])
+        assert info[b] == rinfo == 0
+        assert np.array_equal(perm[b], rperm), (b, int(np.argmax(perm[b] != rperm)))
+        assert np.abs(lu[b] - ref).max() <= 1e-11 * np.abs(ref).max(), (b, np.abs(lu[b] - ref).max())
+    for bad in (-1, 2):
+        with pytest.raises(ss.splitsolve.SplitSolveError):
+            ctx.set_lu_tile(bad)
+
+
 def test_lu_width_rejects_other_values(ctx):
     import paper_1812_01396_amd as ss
     for bad in (-1, 4, 24, 64):
