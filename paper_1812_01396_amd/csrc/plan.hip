@@ -7,8 +7,8 @@
 // instances with more than t blocks are launched, so an uneven chunk does exactly its own work.
 // Groups run on their own streams and overlap.  The enqueued work of each group can be captured once
 // as a short sequence of bounded graph segments, so an execution is a few graph launches per group.  An
-// autotuner times candidate LU panel widths and chunk sizes per group on the group's own smallest
-// instances before capture.
+// autotuner times candidate LU panel widths, LU product tiles and chunk sizes per group on the group's
+// own smallest instances before capture.
 #include <algorithm>
 #include <cmath>
 #include <map>
