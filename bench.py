@@ -650,7 +650,8 @@ class Pipeline:
     """
 
     def __init__(self, workload: str, chunk: int = 0, mode: str = "fp64", refine_tol: float = 1e-10,
-                 accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0, lanes: int = 1):
+                 accept_tol: float = 1e-10, absorb: float | None = None, m: int = 0, lanes: int = 1,
+                 lu_tile: int = 0):
         import torch
 
         import paper_1812_01396_amd as ss
@@ -717,6 +718,8 @@ class Pipeline:
             self.lane_streams.append(st)
             self.lane_ctx.append(ss.Context(0, st))
             self.lane_Q.append(torch.empty(self.chunk, nb, s, 2 * s, dtype=c128, device=dev))
+        for c in self.lane_ctx + [self.ctx_s]:  # tile of the LU's general block products
+            c.set_lu_tile(lu_tile)
         ss.splitsolve._check_kidx(self.kidx, len(insts))  # once: the step itself never reads back to the host
 
     def close(self):
@@ -1065,6 +1068,8 @@ def main():
                     help="absorbing boundary of Step 1 (i*absorb*I on the first and last diagonal blocks; 0: the "
                          "closed A = E S - H; negative: the workload's default)")
     ap.add_argument("--chunk", type=int, default=0, help="instances per Q buffer (0: workload default)")
+    ap.add_argument("--lu-tile", type=int, default=0, choices=[0, 1],
+                    help="tile of the LU's general block products: 0 64 x 64, 1 32 x 64")
     ap.add_argument("--lanes", type=int, default=1,
                     help="split the instances into this many lanes, each with its own context, stream and host "
                          "thread (the refinement's latency-bound tail of one lane overlaps the others' work)")
@@ -1144,7 +1149,7 @@ def main():
     if args.workload == "learned":
         return run_learned(args)
     pipe = Pipeline(args.workload, args.chunk, args.mode, absorb=None if args.absorb < 0 else args.absorb,
-                    refine_tol=args.refine_tol, m=args.m_inj, lanes=args.lanes)
+                    refine_tol=args.refine_tol, m=args.m_inj, lanes=args.lanes, lu_tile=args.lu_tile)
     w, s, nb, m, nbatch = pipe.w, pipe.w["s"], pipe.w["nb"], pipe.w["m"], pipe.n
     fam = args.roofline_kernel
     timed_ctx = pipe.ctx_s if fam in ("dec_update",) else pipe.ctx
