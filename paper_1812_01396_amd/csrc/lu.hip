@@ -572,6 +572,11 @@ __global__ void __launch_bounds__(LB) __attribute__((amdgpu_waves_per_eu(6))) k_
 // ------------------------------------------------------------------ products and triangular leaves
 
 using LuTile = TileCfg<64, 64, 16, 2, 2>;
+// Products of depth kLuG3Depth or more: the three-product form on the same tile (two waves per SIMD);
+// shallower ones keep the four-product form at three waves, where loads and the read-modify-write of
+// the result dominate.
+using LuTileG3 = TileCfgG3<64, 64, 16, 2, 2>;
+constexpr int kLuG3Depth = 128;
 // products of at most 32 rows (the deepest levels of the triangular solves): one row of four waves
 using LuTileFlat = TileCfg<32, 128, 16, 1, 4>;
 // products of at most 32 columns (the depth-32 trailing updates inside a 64-column block): one column
@@ -602,7 +607,7 @@ static_assert(LuTile::NT == 256, "load_perm assumes 256 threads");
 
 // M[r][c] -= sum_{k in [k_lo, k_hi)} M[r][k] M[k][c] for logical rows [r_lo, r_hi), columns [c_lo, c_hi)
 template <class T>
-__global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi,
+__global__ void __launch_bounds__(T::NT) SS_TILE_WAVES_OF(T) k_lu_gemm(LuArgs a, int r_lo, int r_hi, int c_lo, int c_hi,
                                                                 int k_lo, int k_hi) {
   static_assert(T::NT == 256, "load_perm assumes 256 threads");
   __shared__ double lds[T::LDS_DOUBLES];
@@ -766,7 +771,7 @@ __global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W
 // so the 64-deep product between two such leaves needs no launch (and no pass over C) of its own.
 // Each 32 x 32 x 32 product stages both operands in LDS once (four waves, one 16 x 16 block each, on
 // the matrix cores); partial results stay in the accumulators or in LDS.  Requires W = 32, r0 + 64 <= n.
-using LuTileLeaf = TileCfg<32, 32, 32, 2, 2>;
+using LuTileLeaf = TileCfgG3<32, 32, 32, 2, 2>;
 
 template <bool kUpper>
 __global__ void __launch_bounds__(LuTileLeaf::NT) SS_TILE_WAVES k_lu_leaf2x(LuArgs a, int r0, int p0, int c_lo,
@@ -1064,6 +1069,10 @@ struct LuRun {
     } else if (ctx->lu_tile == 1) {
       const int tiles = cdiv(r_hi - r_lo, LuTileHalf::BM) * cdiv(c_hi - c_lo, LuTileHalf::BN);
       hipLaunchKernelGGL(k_lu_gemm<LuTileHalf>, dim3(tiles, d.nmat), dim3(LuTileHalf::NT), 0, ctx->stream, a, r_lo,
+                         r_hi, c_lo, c_hi, k_lo, k_hi);
+    } else if (k_hi - k_lo >= kLuG3Depth) {
+      const int tiles = cdiv(r_hi - r_lo, LuTileG3::BM) * cdiv(c_hi - c_lo, LuTileG3::BN);
+      hipLaunchKernelGGL(k_lu_gemm<LuTileG3>, dim3(tiles, d.nmat), dim3(LuTileG3::NT), 0, ctx->stream, a, r_lo,
                          r_hi, c_lo, c_hi, k_lo, k_hi);
     } else {
       const int tiles = cdiv(r_hi - r_lo, LuTile::BM) * cdiv(c_hi - c_lo, LuTile::BN);

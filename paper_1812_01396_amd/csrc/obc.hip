@@ -22,9 +22,9 @@
 
 namespace ss {
 
-using ObcTile = TileCfg<64, 64, 16, 2, 2>;
+using ObcTile = TileCfgG3<64, 64, 16, 2, 2>;
 // psi = Q (b' + z) has as many columns as injected modes (typically 32): a 64 x 32 tile of four waves
-using PsiTile = TileCfg<64, 32, 16, 4, 1>;
+using PsiTile = TileCfgG3<64, 32, 16, 4, 1>;
 
 // element (r, k) of Q_c = [Q_{1,:}; Q_{nb,:}] (2s x 2s) from Q [nb*s][2s]
 struct LdCorner {
@@ -78,7 +78,7 @@ __device__ __forceinline__ const double2 *obc_q(const ObcArgs &a, int inst) {
   return a.Q + (a.boff ? a.boff[inst] : (long)inst * a.nb) * 2 * (long)a.s * a.s;
 }
 
-__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cq(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES_OF(ObcTile) k_obc_cq(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, nb = obc_nb(a, inst);
@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_cq(ObcArgs a)
 }
 
 // C Q b' into the last m columns of the augmented matrix (m columns: 64 x 32 tiles)
-__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES k_obc_cqb(ObcArgs a) {
+__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES_OF(PsiTile) k_obc_cqb(ObcArgs a) {
   using T = PsiTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;
@@ -135,7 +135,7 @@ __global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES k_obc_cqb(ObcArgs a
 }
 
 // gc = Q_c V
-__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_gc(ObcArgs a) {
+__global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES_OF(ObcTile) k_obc_gc(ObcArgs a) {
   using T = ObcTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s;
@@ -155,7 +155,7 @@ __global__ void __launch_bounds__(ObcTile::NT) SS_TILE_WAVES k_obc_gc(ObcArgs a)
 }
 
 // psi = Q (b' + z): rows nb*s, columns m, depth 2s
-__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES k_obc_psi(ObcArgs a) {
+__global__ void __launch_bounds__(PsiTile::NT) SS_TILE_WAVES_OF(PsiTile) k_obc_psi(ObcArgs a) {
   using T = PsiTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y, s = a.s, m = a.m;

@@ -23,7 +23,7 @@ namespace ss {
 
 // the products of the refinement have m (the injected modes, typically 32) columns: 64 x 32 tiles, no
 // padded half tile
-using RefTile = TileCfg<64, 32, 16, 4, 1>;
+using RefTile = TileCfgG3<64, 32, 16, 4, 1>;
 
 struct LdRowNeg {  // -p[r * ld + c]
   const double2 *p;
@@ -66,16 +66,36 @@ __device__ __forceinline__ int ref_set(const RefArgs &a, int inst) {
   return min(max(k, 0), a.nk - 1);
 }
 
+// Instance-major order for a grid of (work items, instances): linear workgroup ids go to the eight XCDs
+// round-robin, so the ids are remapped such that XCD x runs the instances [x b/8, (x+1) b/8) and takes
+// them work item by work item: the instances that share a momentum (consecutive ones, as the callers
+// order them) then read each (H, S) block panel together through one L2 instead of once per energy.
+// A bijection of the grid; batches that are not a multiple of 8 keep the plain order.
+__device__ __forceinline__ void xcd_inst_order(int &work, int &inst) {
+  const int nw = gridDim.x, nbat = gridDim.y;
+  if (nbat % 8 != 0) {
+    work = blockIdx.x;
+    inst = blockIdx.y;
+    return;
+  }
+  const long lin = blockIdx.x + (long)nw * blockIdx.y;
+  const long slot = lin >> 3;
+  const int per = nbat >> 3;
+  inst = (int)(lin & 7) * per + (int)(slot % per);
+  work = (int)(slot / per);
+}
+
 // r = B b' - T x for every block, with ||r||^2 and ||B b'||^2; grid (nb * tiles(s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_resid(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES_OF(RefTile) k_ref_resid(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ double red[2][T::NT / 64];
-  const int inst = blockIdx.y;
+  int work, inst;
+  xcd_inst_order(work, inst);
   if (a.done[inst]) return;
   const int s = a.s, m = a.m, nb = a.nb;
   const int tr = cdiv(s, T::BM), tc = cdiv(m, T::BN);
-  const int i = blockIdx.x / (tr * tc), rem = blockIdx.x % (tr * tc);
+  const int i = work / (tr * tc), rem = work % (tr * tc);
   const int m0 = (rem / tc) * T::BM, n0 = (rem % tc) * T::BN;
   const int ks = ref_set(a, inst);
   const double e = a.E[inst];
@@ -152,14 +172,15 @@ __global__ void k_ref_check(RefArgs a, int it, int *iters, double *resid) {
 }
 
 // r_i -= A_{i,i+1} g_{i+1}
-__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_couple(RefArgs a, int i) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES_OF(RefTile) k_ref_couple(RefArgs a, int i) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
-  const int inst = blockIdx.y;
+  int tile, inst;
+  xcd_inst_order(tile, inst);
   if (a.done[inst]) return;
   const int s = a.s, m = a.m, nb = a.nb;
   const int tc = cdiv(m, T::BN);
-  const int m0 = (blockIdx.x / tc) * T::BM, n0 = (blockIdx.x % tc) * T::BN;
+  const int m0 = (tile / tc) * T::BM, n0 = (tile % tc) * T::BN;
   const int ks = ref_set(a, inst);
   const double e = a.E[inst];
   const long ss2 = (long)s * s, sm = (long)s * m;
@@ -176,7 +197,7 @@ __global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_couple(RefArg
 }
 
 // y_i = g_i - X_i y_{i-1} (in place in g); X_i of block i was kept at slot nb-1-i of the even system
-__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_chain(RefArgs a, int i) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES_OF(RefTile) k_ref_chain(RefArgs a, int i) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -198,7 +219,7 @@ __global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_chain(RefArgs
 }
 
 // C y = [Sigma_L y_1; Sigma_R y_nb]; grid (2 * tiles(s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_cy(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES_OF(RefTile) k_ref_cy(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;
@@ -228,7 +249,7 @@ __global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_cy(RefArgs a)
 }
 
 // x += y + Q z; grid (tiles(nb s) * tiles(m), batch)
-__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES k_ref_update(RefArgs a) {
+__global__ void __launch_bounds__(RefTile::NT) SS_TILE_WAVES_OF(RefTile) k_ref_update(RefArgs a) {
   using T = RefTile;
   __shared__ double lds[T::LDS_DOUBLES];
   const int inst = blockIdx.y;

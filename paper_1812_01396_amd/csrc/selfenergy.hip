@@ -109,10 +109,11 @@ __global__ void k_dec_reset(DecArgs a) {
 }
 
 using DecTile = TileCfg<64, 64, 16, 2, 2>;
+using DecTileG3 = TileCfgG3<64, 64, 16, 2, 2>;
 
 // One decimation pass for tile (m0, n0) of every s x s block, from Y = [G beta | G alpha].
-__global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES k_dec_update(DecArgs a, int par) {
-  using T = DecTile;
+__global__ void __launch_bounds__(DecTile::NT) SS_TILE_WAVES_OF(DecTileG3) k_dec_update(DecArgs a, int par) {
+  using T = DecTileG3;
   __shared__ double lds[T::LDS_DOUBLES];
   int tile, inst;
   xcd_tile_order(tile, inst);

@@ -5,7 +5,9 @@
 // with A and B fetched through loader functors (plain row-major, row-permuted, conjugate-transposed,
 // or formed on the fly as E*S - H).  Operands are staged through LDS as separate real and imaginary
 // planes laid out [k][m] and [k][n], so each MFMA operand read is 16 consecutive doubles per k row.
-// A complex product is four real MFMAs (re*re - im*im, re*im + im*re); the next stage's global loads
+// A complex product is four real MFMAs (re*re - im*im, re*im + im*re), or, for tile configurations of
+// type TileCfgG3, three (Gauss's method: ArBr, AiBi and (Ar+Ai)(Br+Bi) summed separately, the real part
+// the first minus the second, the imaginary part the third minus both); the next stage's global loads
 // are issued before the current stage's MFMAs so their latency hides behind the matrix work.
 //
 // Register layout of v_mfma_f64_16x16x4_f64 (wave64), measured on gfx950:
@@ -21,6 +23,8 @@
 // per SIMD); measured on batched 64 x 64 x k products, three waves are 12-20 % faster, four spill.
 // (Kernels whose budget would spill at 168, such as the FP32-product variants, keep the default.)
 #define SS_TILE_WAVES __attribute__((amdgpu_waves_per_eu(3)))
+// The same for a kernel whose budget follows its tile configuration (T::WAVES waves per SIMD).
+#define SS_TILE_WAVES_OF(T) __attribute__((amdgpu_waves_per_eu(T::WAVES)))
 
 namespace ss {
 
@@ -35,15 +39,33 @@ struct TileCfg {
   static constexpr int LDS_DOUBLES = 2 * BK * PA + 2 * BK * PB;
   static constexpr int EA = (BM * BK + NT - 1) / NT;
   static constexpr int EB = (BK * BN + NT - 1) / NT;
+  static constexpr bool G3 = false;  // three-product complex multiply (TileCfgG3)
+  static constexpr int WAVES = 3;    // waves per SIMD the register budget is set for
   static_assert(FM >= 1 && FN >= 1, "tile smaller than one MFMA block per wave");
   static_assert(FM * 16 * WM == BM && FN * 16 * WN == BN, "tile not a multiple of the wave grid");
   static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA depth");
 };
 
+// Gauss's three-product complex multiply: the same tile with 3/4 of the matrix-core work, at the cost
+// of a third accumulator set (8 FM FN more registers per lane) and FM + FN additions per k step.  Its
+// rounding error is bounded normwise like the four-product form's, with (|Ar| + |Ai|)(|Br| + |Bi|) in
+// place of the products of the parts in the imaginary part's bound.  With four or more MFMA blocks per
+// wave the accumulators (96 registers) leave too little of a 168-register budget: two waves per SIMD.
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct TileCfgG3 : TileCfg<BM_, BN_, BK_, WM_, WN_> {
+  using Base = TileCfg<BM_, BN_, BK_, WM_, WN_>;
+  static constexpr bool G3 = true;
+  static constexpr int WAVES = Base::FM * Base::FN >= 4 ? 2 : 3;
+};
+
+// Accumulators.  Four-product form: re and im are the real and imaginary parts.  Three-product form:
+// re = sum Ar Br, im = sum (Ar + Ai)(Br + Bi), x = sum Ai Bi (acc_foreach and value() combine them).
 template <class T>
 struct Acc {
+  static constexpr int XM = T::G3 ? T::FM : 1, XN = T::G3 ? T::FN : 1;
   v4d re[T::FM][T::FN];
   v4d im[T::FM][T::FN];
+  v4d x[XM][XN];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int i = 0; i < T::FM; ++i)
@@ -52,6 +74,21 @@ struct Acc {
         re[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
         im[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
       }
+    if constexpr (T::G3) {
+#pragma unroll
+      for (int i = 0; i < XM; ++i)
+#pragma unroll
+        for (int j = 0; j < XN; ++j) x[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+    }
+  }
+  // the complex value of element q of block (i, j)
+  __device__ __forceinline__ double2 value(int i, int j, int q) const {
+    if constexpr (T::G3) {
+      const double t1 = re[i][j][q], t2 = x[i][j][q];
+      return make_double2(t1 - t2, im[i][j][q] - t1 - t2);
+    } else {
+      return make_double2(re[i][j][q], im[i][j][q]);
+    }
   }
 };
 
@@ -131,27 +168,51 @@ __device__ __forceinline__ void mma_stage(const Lds<T> &L, Acc<T> &acc) {
 #pragma unroll
   for (int ks = 0; ks < KSTEPS; ++ks) {
     const int kr = ks * 4 + (lane >> 4);
-    double ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+    if constexpr (T::G3) {
+      double ar[T::FM], ai[T::FM], as[T::FM], br[T::FN], bi[T::FN], bs[T::FN];
 #pragma unroll
-    for (int i = 0; i < T::FM; ++i) {
-      ar[i] = L.ar[kr * T::PA + mbase + i * 16];
-      ai[i] = L.ai[kr * T::PA + mbase + i * 16];
-      an[i] = -ai[i];
-    }
-#pragma unroll
-    for (int j = 0; j < T::FN; ++j) {
-      br[j] = L.br[kr * T::PB + nbase + j * 16];
-      bi[j] = L.bi[kr * T::PB + nbase + j * 16];
-    }
-#pragma unroll
-    for (int i = 0; i < T::FM; ++i)
+      for (int i = 0; i < T::FM; ++i) {
+        ar[i] = L.ar[kr * T::PA + mbase + i * 16];
+        ai[i] = L.ai[kr * T::PA + mbase + i * 16];
+        as[i] = ar[i] + ai[i];
+      }
 #pragma unroll
       for (int j = 0; j < T::FN; ++j) {
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
-        acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], acc.re[i][j], 0, 0, 0);
-        acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+        br[j] = L.br[kr * T::PB + nbase + j * 16];
+        bi[j] = L.bi[kr * T::PB + nbase + j * 16];
+        bs[j] = br[j] + bi[j];
       }
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j) {
+          acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+          acc.x[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], bi[j], acc.x[i][j], 0, 0, 0);
+          acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(as[i], bs[j], acc.im[i][j], 0, 0, 0);
+        }
+    } else {
+      double ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i) {
+        ar[i] = L.ar[kr * T::PA + mbase + i * 16];
+        ai[i] = L.ai[kr * T::PA + mbase + i * 16];
+        an[i] = -ai[i];
+      }
+#pragma unroll
+      for (int j = 0; j < T::FN; ++j) {
+        br[j] = L.br[kr * T::PB + nbase + j * 16];
+        bi[j] = L.bi[kr * T::PB + nbase + j * 16];
+      }
+#pragma unroll
+      for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j) {
+          acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+          acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
+          acc.re[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(an[i], bi[j], acc.re[i][j], 0, 0, 0);
+          acc.im[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+        }
+    }
   }
 }
 
@@ -231,7 +292,7 @@ __device__ __forceinline__ void acc_foreach(const Acc<T> &acc, F &&f) {
       for (int q = 0; q < 4; ++q) {
         const int r = wm * T::FM * 16 + i * 16 + 4 * q + (lane >> 4);
         const int c = wn * T::FN * 16 + j * 16 + (lane & 15);
-        f(r, c, make_double2(acc.re[i][j][q], acc.im[i][j][q]));
+        f(r, c, acc.value(i, j, q));
       }
 }
 

@@ -28,15 +28,25 @@ struct TileCfg32 {
   static constexpr int LDS_FLOATS = 2 * BK * PA + 2 * BK * PB;
   static constexpr int EA = (BM * BK + NT - 1) / NT;
   static constexpr int EB = (BK * BN + NT - 1) / NT;
+  static constexpr bool G3 = false;  // three-product complex multiply (TileCfg32G3)
   static_assert(FM >= 1 && FN >= 1, "tile smaller than one MFMA block per wave");
   static_assert(FM * 16 * WM == BM && FN * 16 * WN == BN, "tile not a multiple of the wave grid");
   static_assert(BK % 4 == 0, "BK must be a multiple of the MFMA depth");
 };
 
+// Gauss's three-product complex multiply, as for the FP64 engine: re = sum Ar Br, im = sum (Ar + Ai)(Br + Bi),
+// x = sum Ai Bi; the parts are combined in FP32 before the result leaves the engine.
+template <int BM_, int BN_, int BK_, int WM_, int WN_>
+struct TileCfg32G3 : TileCfg32<BM_, BN_, BK_, WM_, WN_> {
+  static constexpr bool G3 = true;
+};
+
 template <class T>
 struct Acc32 {
+  static constexpr int XM = T::G3 ? T::FM : 1, XN = T::G3 ? T::FN : 1;
   v4f re[T::FM][T::FN];
   v4f im[T::FM][T::FN];
+  v4f x[XM][XN];
   __device__ __forceinline__ void zero() {
 #pragma unroll
     for (int i = 0; i < T::FM; ++i)
@@ -45,6 +55,20 @@ struct Acc32 {
         re[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
         im[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
       }
+    if constexpr (T::G3) {
+#pragma unroll
+      for (int i = 0; i < XM; ++i)
+#pragma unroll
+        for (int j = 0; j < XN; ++j) x[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+  }
+  __device__ __forceinline__ double2 value(int i, int j, int q) const {
+    if constexpr (T::G3) {
+      const float t1 = re[i][j][q], t2 = x[i][j][q];
+      return make_double2((double)(t1 - t2), (double)(im[i][j][q] - t1 - t2));
+    } else {
+      return make_double2((double)re[i][j][q], (double)im[i][j][q]);
+    }
   }
 };
 
@@ -112,27 +136,51 @@ __device__ __forceinline__ void mma_loop32(const LA &la, const LB &lb, int m0, i
 #pragma unroll
     for (int ks = 0; ks < T::BK / 4; ++ks) {
       const int kr = ks * 4 + (lane >> 4);
-      float ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+      if constexpr (T::G3) {
+        float ar[T::FM], ai[T::FM], as[T::FM], br[T::FN], bi[T::FN], bs[T::FN];
 #pragma unroll
-      for (int i = 0; i < T::FM; ++i) {
-        ar[i] = sar[kr * T::PA + mbase + i * 16];
-        ai[i] = sai[kr * T::PA + mbase + i * 16];
-        an[i] = -ai[i];
-      }
-#pragma unroll
-      for (int j = 0; j < T::FN; ++j) {
-        br[j] = sbr[kr * T::PB + nbase + j * 16];
-        bi[j] = sbi[kr * T::PB + nbase + j * 16];
-      }
-#pragma unroll
-      for (int i = 0; i < T::FM; ++i)
+        for (int i = 0; i < T::FM; ++i) {
+          ar[i] = sar[kr * T::PA + mbase + i * 16];
+          ai[i] = sai[kr * T::PA + mbase + i * 16];
+          as[i] = ar[i] + ai[i];
+        }
 #pragma unroll
         for (int j = 0; j < T::FN; ++j) {
-          acc.re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], acc.re[i][j], 0, 0, 0);
-          acc.im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
-          acc.re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[i], bi[j], acc.re[i][j], 0, 0, 0);
-          acc.im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+          br[j] = sbr[kr * T::PB + nbase + j * 16];
+          bi[j] = sbi[kr * T::PB + nbase + j * 16];
+          bs[j] = br[j] + bi[j];
         }
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::FN; ++j) {
+            acc.re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+            acc.x[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], bi[j], acc.x[i][j], 0, 0, 0);
+            acc.im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[i], bs[j], acc.im[i][j], 0, 0, 0);
+          }
+      } else {
+        float ar[T::FM], ai[T::FM], an[T::FM], br[T::FN], bi[T::FN];
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i) {
+          ar[i] = sar[kr * T::PA + mbase + i * 16];
+          ai[i] = sai[kr * T::PA + mbase + i * 16];
+          an[i] = -ai[i];
+        }
+#pragma unroll
+        for (int j = 0; j < T::FN; ++j) {
+          br[j] = sbr[kr * T::PB + nbase + j * 16];
+          bi[j] = sbi[kr * T::PB + nbase + j * 16];
+        }
+#pragma unroll
+        for (int i = 0; i < T::FM; ++i)
+#pragma unroll
+          for (int j = 0; j < T::FN; ++j) {
+            acc.re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], br[j], acc.re[i][j], 0, 0, 0);
+            acc.im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[i], bi[j], acc.im[i][j], 0, 0, 0);
+            acc.re[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(an[i], bi[j], acc.re[i][j], 0, 0, 0);
+            acc.im[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[i], br[j], acc.im[i][j], 0, 0, 0);
+          }
+      }
     }
   }
 }
@@ -149,7 +197,7 @@ __device__ __forceinline__ void acc_foreach32(const Acc32<T> &acc, F &&f) {
       for (int q = 0; q < 4; ++q) {
         const int r = wm * T::FM * 16 + i * 16 + 4 * (lane >> 4) + q;
         const int c = wn * T::FN * 16 + j * 16 + (lane & 15);
-        f(r, c, make_double2((double)acc.re[i][j][q], (double)acc.im[i][j][q]));
+        f(r, c, acc.value(i, j, q));
       }
 }
 
