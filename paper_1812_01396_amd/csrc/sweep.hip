@@ -95,7 +95,8 @@ enum { kProdF64 = 0, kProdF32 = 1, kProdBF16 = 2 };
 
 // acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in the precision kP; f(r, c, value) receives
 // every element of the tile.  kG3: FP64 products in the three-product form (the chain; the formation,
-// whose loads form E S - H, runs faster with the four-product form's third wave per SIMD).
+// whose loads form E S - H, runs faster with the four-product form's third wave per SIMD).  FP32
+// products always take the three-product form (its accumulators still fit three waves).
 template <int kP, bool kG3, class LA, class LB, class F>
 __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0, int M, int n0, int N, int kbeg,
                                              int kend, double *lds, F &&f) {
@@ -214,48 +215,30 @@ __device__ __forceinline__ void form_body(const SweepArgs &a, int t, double *lds
     // is also written, in FP32: A_{ib-1,ib} = E S_u - H_u (direction 0), A_{ib+1,ib} = its transpose
     // conjugate (direction 1)
     float2 *cp = (kPart == 2 && !ident) ? a.cpl + (long)mat * ss2 : nullptr;
-    // F = E S_u - H_u of block ub.  The outputs that take F itself are written from row-wise reads; the
-    // ones that take F^H (the RHS in direction 0, the FP32 coupling in direction 1) go through LDS in
-    // four slices of 16 source rows, so that reads and writes both run along rows.
-    auto fval = [&](int r, int c) {
-      const long o = (long)r * s + c;
-      return make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
-    };
     for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT) {
       const int r = idx / T::BN, c = idx % T::BN;
       const int gr = m0 + r, gc = n0 + c;
       if (gr >= s || gc >= s) continue;
-      if (ident) {
-        M[(long)gr * 2 * s + s + gc] = make_double2(gr == gc ? 1.0 : 0.0, 0.0);
-      } else if (dir == 1) {
-        M[(long)gr * 2 * s + s + gc] = fval(gr, gc);
-      } else if (cp) {
-        const double2 w = fval(gr, gc);
-        cp[(long)gr * s + gc] = make_float2((float)w.x, (float)w.y);
+      double2 v;
+      if (ident) v = make_double2(gr == gc ? 1.0 : 0.0, 0.0);
+      else if (dir == 0) {  // (E S_u - H_u)^H element (gr, gc) = conj(E S_u[gc][gr] - H_u[gc][gr])
+        const long o = (long)gc * s + gr;
+        v = make_double2(e * su[o].x - hu[o].x, -(e * su[o].y - hu[o].y));
+      } else {
+        const long o = (long)gr * s + gc;
+        v = make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
       }
-    }
-    if (!ident && (dir == 0 || cp)) {
-      constexpr int SL = 16, PT = T::BM + 1;
-      static_assert(T::BN % SL == 0 && 2 * SL * PT <= T::LDS_DOUBLES, "transpose slice");
-      double *tre = lds, *tim = lds + SL * PT;
-      for (int q = 0; q < T::BN; q += SL) {
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < SL * T::BM; idx += T::NT) {  // F[n0+q+rr][m0+cc]
-          const int rr = idx / T::BM, cc = idx % T::BM;
-          const int sr = n0 + q + rr, sc = m0 + cc;
-          const double2 v = (sr < s && sc < s) ? fval(sr, sc) : make_double2(0.0, 0.0);
-          tre[rr * PT + cc] = v.x;
-          tim[rr * PT + cc] = v.y;
+      M[(long)gr * 2 * s + s + gc] = v;
+      if (cp) {
+        double2 w;
+        if (dir == 0) {
+          const long o = (long)gr * s + gc;
+          w = make_double2(e * su[o].x - hu[o].x, e * su[o].y - hu[o].y);
+        } else {
+          const long o = (long)gc * s + gr;
+          w = make_double2(e * su[o].x - hu[o].x, -(e * su[o].y - hu[o].y));
         }
-        __syncthreads();
-        for (int idx = threadIdx.x; idx < T::BM * SL; idx += T::NT) {  // output (m0+lr, n0+q+lc) = conj F^T
-          const int lr = idx / SL, lc = idx % SL;
-          const int gr = m0 + lr, gc = n0 + q + lc;
-          if (gr >= s || gc >= s) continue;
-          const double vr = tre[lc * PT + lr], vi = -tim[lc * PT + lr];
-          if (dir == 0) M[(long)gr * 2 * s + s + gc] = make_double2(vr, vi);
-          else cp[(long)gr * s + gc] = make_float2((float)vr, (float)vi);
-        }
+        cp[(long)gr * s + gc] = make_float2((float)w.x, (float)w.y);
       }
     }
   }
@@ -295,8 +278,7 @@ __global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_
 }
 
 __global__ void __launch_bounds__(FormTile::NT) k_form_rhs(SweepArgs a, int t) {
-  __shared__ double lds[2 * 16 * (FormTile::BM + 1)];  // the transpose slices
-  form_body<kProdF64, 2>(a, t, lds);
+  form_body<kProdF64, 2>(a, t, nullptr);
 }
 
 // Chain step u: Q_ib = -X(slot nb-1-u) Q_prev (u > 0), or a copy of the slot (u == 0).
