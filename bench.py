@@ -270,7 +270,8 @@ def counter_means(path: str, pattern: str):
 
 
 # kernel families of the SQ counter report: (label, name pattern)
-SQ_FAMILIES = [("k_lu_gemm 64x64", r"k_lu_gemm<ss::TileCfg<64, 64"), ("k_lu_gemm 64x32", r"k_lu_gemm<ss::TileCfg<64, 32"),
+SQ_FAMILIES = [("k_lu_gemm 64x64", r"k_lu_gemm<ss::TileCfg<64, 64"),
+               ("k_lu_gemm 64x64 G3", r"k_lu_gemm<ss::TileCfgG3<64, 64"), ("k_lu_gemm 64x32", r"k_lu_gemm<ss::TileCfg<64, 32"),
                ("k_lu_gemm 32x128", r"k_lu_gemm<ss::TileCfg<32, 128"), ("k_panel32", r"k_panel32<"),
                ("k_lu_leaf2x", r"k_lu_leaf2x<"), ("k_form", r"k_form<"), ("k_chain", r"k_chain<"),
                ("k_dec_update", r"k_dec_update")]
