@@ -16,7 +16,7 @@
 namespace ss {
 
 // psi has as many columns as injected modes (typically 32): 64 x 32 tiles of four waves
-using ObsTile = TileCfg<64, 32, 16, 4, 1>;
+using ObsTile = TileCfgG3<64, 32, 16, 4, 1>;
 
 struct LdHerm {  // element (r, c) of P^H for row-major P: conj(p[c * ld + r])
   const double2 *p;
@@ -46,7 +46,7 @@ __global__ void k_obs_zero(double *p, long n) {
 }
 
 // grid (tiles(s) * tiles(m), nb, batch)
-__global__ void __launch_bounds__(ObsTile::NT) SS_TILE_WAVES k_obs_density(ObsArgs a) {
+__global__ void __launch_bounds__(ObsTile::NT) SS_TILE_WAVES_OF(ObsTile) k_obs_density(ObsArgs a) {
   using T = ObsTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ double rowsum[T::BM];
@@ -94,7 +94,7 @@ __global__ void __launch_bounds__(ObsTile::NT) SS_TILE_WAVES k_obs_density(ObsAr
 }
 
 // grid (tiles(s) * tiles(m), nb - 1, batch)
-__global__ void __launch_bounds__(ObsTile::NT) SS_TILE_WAVES k_obs_current(ObsArgs a) {
+__global__ void __launch_bounds__(ObsTile::NT) SS_TILE_WAVES_OF(ObsTile) k_obs_current(ObsArgs a) {
   using T = ObsTile;
   __shared__ double lds[T::LDS_DOUBLES];
   __shared__ double red[T::NT / 64];
