@@ -18,7 +18,6 @@
 // Q'_{nb-1} = Y_{nb-1}) both read slot nb-1-u at chain step u and write into the caller's Q.
 #include <algorithm>
 #include <climits>
-#include <type_traits>
 
 #include "lu.hpp"
 #include "drivers.hpp"
@@ -94,10 +93,9 @@ static_assert(FormTileB::NT == FormTile::NT, "one workgroup shape for every prec
 enum { kProdF64 = 0, kProdF32 = 1, kProdBF16 = 2 };
 
 // acc(r, c) = sum_k A(r, k) B(k, c) over one 64 x 64 tile in the precision kP; f(r, c, value) receives
-// every element of the tile.  kG3: FP64 products in the three-product form (the chain; the formation,
-// whose loads form E S - H, runs faster with the four-product form's third wave per SIMD).  FP32
-// products always take the three-product form (its accumulators still fit three waves).
-template <int kP, bool kG3, class LA, class LB, class F>
+// every element of the tile.  FP64 and FP32 products take the three-product form (two waves per SIMD for
+// FP64, three for FP32); the BF16-term products keep four real products.
+template <int kP, class LA, class LB, class F>
 __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0, int M, int n0, int N, int kbeg,
                                              int kend, double *lds, F &&f) {
   if constexpr (kP == kProdF32) {
@@ -111,11 +109,10 @@ __device__ __forceinline__ void tile_product(const LA &la, const LB &lb, int m0,
     mma_loop_bf<FormTileB>(la, lb, m0, M, n0, N, kbeg, kend, acc, reinterpret_cast<unsigned short *>(lds));
     acc_foreach_bf<FormTileB>(acc, f);
   } else {
-    using T = std::conditional_t<kG3, FormTileG3, FormTile>;
-    Acc<T> acc;
+    Acc<FormTileG3> acc;
     acc.zero();
-    mma_loop<T>(la, lb, m0, M, n0, N, kbeg, kend, acc, lds);
-    acc_foreach<T>(acc, f);
+    mma_loop<FormTileG3>(la, lb, m0, M, n0, N, kbeg, kend, acc, lds);
+    acc_foreach<FormTileG3>(acc, f);
   }
 }
 
@@ -189,10 +186,10 @@ __device__ __forceinline__ void form_body(const SweepArgs &a, int t, double *lds
         });
       } else if (dir == 0) {  // A_{ib,ib+1} = E S_u[ib] - H_u[ib]
         LdForm<false> la{blk(a, ks, 1, ib), blk(a, ks, 3, ib), s, e};
-        tile_product<kP, false>(la, lb, m0, s, n0, s, 0, s, lds, store);
+        tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, store);
       } else {  // A_{ib,ib-1} = (E S_u[ib-1] - H_u[ib-1])^H
         LdForm<true> la{blk(a, ks, 1, ib - 1), blk(a, ks, 3, ib - 1), s, e};
-        tile_product<kP, false>(la, lb, m0, s, n0, s, 0, s, lds, store);
+        tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, store);
       }
     } else {
       for (int idx = threadIdx.x; idx < T::BM * T::BN; idx += T::NT)
@@ -265,7 +262,7 @@ __global__ void k_code_init(int *code, int n) {
 }
 
 template <bool kF32>
-__global__ void __launch_bounds__(FormTile::NT) SS_TILE_WAVES k_form(SweepArgs a, int t) {
+__global__ void __launch_bounds__(FormTile::NT) __attribute__((amdgpu_waves_per_eu(kF32 ? 3 : FormTileG3::WAVES))) k_form(SweepArgs a, int t) {
   __shared__ double lds[FormTile::LDS_DOUBLES];
   form_body<kF32 ? kProdF32 : kProdF64, 0>(a, t, lds);
 }
@@ -308,7 +305,7 @@ __device__ __forceinline__ void chain_body(const SweepArgs &a, int u, double *ld
   const double2 *qp = q0 + (long)pb * 2 * ss2;
   LdRow la{x, s};
   LdRow lb{qp, 2 * s};
-  tile_product<kP, true>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
+  tile_product<kP>(la, lb, m0, s, n0, s, 0, s, lds, [&](int r, int c, double2 v) {
     const int gr = m0 + r, gc = n0 + c;
     if (gr < s && gc < s) qi[(long)gr * 2 * s + gc] = cneg(v);
   });
