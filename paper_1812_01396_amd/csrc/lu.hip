@@ -770,8 +770,7 @@ __global__ void __launch_bounds__(T::NT) SS_TILE_WAVES k_lu_leaf(LuArgs a, int W
 // 64-row block already solved at rows p0 (C -= F X_p, F the factors' block at rows r0, columns p0),
 // so the 64-deep product between two such leaves needs no launch (and no pass over C) of its own.
 // Each 32 x 32 x 32 product stages both operands in LDS once (four waves, one 16 x 16 block each, on
-// the matrix cores in the three-product form, which still fits three waves per SIMD); partial results
-// stay in the accumulators or in LDS.  Requires W = 32, r0 + 64 <= n.
+// the matrix cores); partial results stay in the accumulators or in LDS.  Requires W = 32, r0 + 64 <= n.
 using LuTileLeaf = TileCfgG3<32, 32, 32, 2, 2>;
 
 template <bool kUpper>
